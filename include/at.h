@@ -1,0 +1,212 @@
+/*
+ * at.h -- C ABI of libat.so, the MI355X (gfx950) stepper for explicit
+ * time-marching of viscous Burgers' equation with asynchrony-tolerant (AT)
+ * finite differences at subdomain boundaries, after Aditya, Gysi,
+ * Kwasniewski, Hoefler, Donzis and Chen, "A scalable weakly-synchronous
+ * algorithm for solving partial differential equations" (arXiv:1911.05769).
+ *
+ * The method (paper sections 2, 3 and 5.2):
+ *   * The grid is split into P subdomains ("processing elements" in the
+ *     paper, tiles of one device-resident grid here).  A point whose stencil
+ *     reaches into another tile reads that tile's edge through a halo whose
+ *     value may lag the current level n by a delay k, 0 <= k <= L
+ *     (section 2).  Delays are prescribed per directed face and per step.
+ *   * The halo value is extrapolated in time from the m most recent
+ *     available levels n-k, n-k-1, ... of the neighbour's edge (the AT
+ *     schemes, section 2, Eqs. (1)-(2): weights (k+1, -k) for m = 2).  The
+ *     stencil itself is the standard central one (section 5.2 splits AT into
+ *     "halo approximation" and "unchanged stencil").  Order 4 uses m = 3
+ *     (quadratic Newton extrapolation in time; the paper defers the 4th-order
+ *     coefficients to another article).
+ *   * Central differences, forward Euler (section 3.2), for
+ *     u_t + u u_x = nu u_xx (1D) and u_i,t + u_j d_j u_i = nu d_j d_j u_i (3D
+ *     vector, section 3.1, Eq. (4)), periodic domain of side `length`.
+ *   * The neighbour edges of past levels live in a circular buffer ("ring")
+ *     of R levels, the analogue of the paper's circular receive buffers of
+ *     T entries (section 5.2, Algorithm 2, Table 1).
+ *
+ * Conventions for every call:
+ *   * All field pointers (u, scratch, lambda, gradients, targets, outputs of
+ *     reductions) are DEVICE pointers to contiguous binary64 arrays owned by
+ *     the caller.  1D fields are double[n0].  3D fields are double[3][nz][ny][nx]
+ *     (component-major, x fastest).
+ *   * The caller also owns the workspace (device memory of at least
+ *     at_workspace_bytes() bytes, 256-byte aligned).  The library never
+ *     allocates or frees device memory.  The opaque handles (at_ctx,
+ *     at_batch) hold host-side state only.
+ *   * Calls are asynchronous on the stream given in the configuration unless
+ *     stated otherwise; results meant for the host are written to device
+ *     memory.  Calls on one context must not overlap.
+ *   * Every call returns an at_status; on failure it changes nothing it
+ *     documents as output, and at_last_error() returns a message.  No call
+ *     aborts or throws.
+ */
+#ifndef AT_H
+#define AT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AT_ABI_VERSION 1
+
+typedef enum {
+    AT_OK = 0,
+    AT_ERR_ARG = -1,     /* invalid argument or configuration field        */
+    AT_ERR_SHAPE = -2,   /* n % p != 0, tile narrower than the stencil, ... */
+    AT_ERR_DELAY = -3,   /* a delay outside 0..min(L, max(0, n-m+1))       */
+    AT_ERR_HIP = -4,     /* a HIP runtime call failed (message kept)       */
+    AT_ERR_NOMEM = -5,   /* workspace too small                            */
+    AT_ERR_STATE = -6    /* call not valid in the context's current state  */
+} at_status;
+
+/* Delay sources and distributions. */
+#define AT_DELAY_GENERATE 0   /* k[n][f] from the counter-based generator      */
+#define AT_DELAY_HOST 1       /* k[n][f] copied from delays_host (validated)   */
+#define AT_DIST_UNIFORM 0     /* k uniform on {0..L}                           */
+#define AT_DIST_HALF_ZERO 1   /* k = 0 with probability 1/2, else {1..L}       */
+
+typedef struct at_config {
+    int32_t abi_version;      /* must equal AT_ABI_VERSION                        */
+    int32_t dim;              /* 1 (scalar) or 3 (vector, 3 components)           */
+    int64_t n[3];             /* points per axis x, y, z (1D: n[1] = n[2] = 1)    */
+    int32_t p[3];             /* tiles per axis (1D: p[1] = p[2] = 1)             */
+    int32_t order;            /* 2 or 4 (3D: 2); halo width h = order / 2,
+                                 extrapolation levels m = 2 (order 2), 3 (order 4) */
+    int32_t L;                /* maximum delay, 0..15 (section 2)                 */
+    int32_t halo_mode;        /* 0: AT extrapolation; 1: standard scheme on the
+                                 delayed level n-k (the paper's negative control)  */
+    int32_t adv_mode;         /* 0: Burgers u u_x; 1 (1D only): linear
+                                 advection c u_x with c = adv_speed                */
+    double nu;                /* viscosity, >= 0                                  */
+    double dt;                /* time step, > 0, constant for the run             */
+    double length;            /* side of the periodic domain (dx = length / n)    */
+    double adv_speed;         /* c for adv_mode 1                                 */
+    int32_t delay_mode;       /* AT_DELAY_GENERATE or AT_DELAY_HOST               */
+    int32_t delay_dist;       /* AT_DIST_* (generate mode)                        */
+    uint64_t delay_seed;      /* generator seed (generate mode)                   */
+    const int8_t *delays_host;/* host array int8[nsteps_max][F] (host mode);
+                                 F = 2*p[0] (1D) or 6*p[0]*p[1]*p[2] (3D);
+                                 face f = 2*tile + side (1D), 6*block + 2*axis +
+                                 side (3D), side 0 = low, 1 = high; the block
+                                 index is (bz*p[1] + by)*p[0] + bx               */
+    int64_t nsteps_max;       /* steps the context may advance in total          */
+    int32_t record;           /* 1: keep what at_adjoint needs (1D only)          */
+    int32_t ckpt_every;       /* record mode: checkpoint interval C >= 1          */
+    int32_t fuse_steps;       /* steps per launch s (1 = one launch per step);
+                                 0 = let at_autotune choose (default 1 until then) */
+    int32_t reserved0;
+    void *stream;             /* hipStream_t for all work of this context         */
+    void *workspace;          /* device memory owned by the caller                */
+    uint64_t workspace_bytes;
+} at_config;
+
+typedef struct at_ctx at_ctx;
+
+/* Bytes of device workspace needed by `cfg` (the workspace fields are
+ * ignored).  Host-only; no device work. */
+at_status at_workspace_bytes(const at_config *cfg, uint64_t *bytes);
+
+/* Validate `cfg`, lay out the workspace, fill the delay array k[n][f]
+ * (section 2; generate mode: SplitMix64 output of seed + gamma*(1 + n*F + f),
+ * mapped to the distribution, then clamped to min(k, max(0, n - m + 1)) so no
+ * level below 0 is read -- the start-up synchrony of Algorithm 2; host mode:
+ * copied after checking every entry against that bound, AT_ERR_DELAY if one
+ * fails) and clear the ring.  The context starts at step n = 0.  Synchronises
+ * the stream once before returning. */
+at_status at_init(const at_config *cfg, at_ctx **out);
+
+/* Release the handle (host memory only; the workspace stays the caller's). */
+void at_free(at_ctx *ctx);
+
+/* One step n -> n+1 in the one-launch-per-step form: reads u_in (level n),
+ * writes u_out (level n+1), publishes level n's tile edges to the ring.
+ * u_in and u_out must not overlap.  AT_ERR_STATE past nsteps_max. */
+at_status at_step(at_ctx *ctx, const double *u_in, double *u_out);
+
+/* Advance nsteps steps from the current level held in u; the result is left
+ * in u.  scratch is a second field of the same size.  Steps are fused s at a
+ * time (fuse_steps or the autotuned value); results are bit-identical for
+ * every s.  Record mode also stores a checkpoint of u every ckpt_every
+ * steps, counted from n = 0. */
+at_status at_run(at_ctx *ctx, double *u, double *scratch, int64_t nsteps);
+
+/* Choose steps-per-launch s (and nothing else that changes results) by timing
+ * `trial_steps` steps from u0 for each candidate; requires n == 0 and leaves
+ * the context at n = 0 with the ring cleared.  u0 is not modified; t1 and t2
+ * are two scratch fields.  Synchronises the stream.  *chosen receives s. */
+at_status at_autotune(at_ctx *ctx, const double *u0, double *t1, double *t2,
+                      int32_t trial_steps, int32_t *chosen);
+
+/* Current step n, steps per launch in use, ring levels R. */
+at_status at_query(const at_ctx *ctx, int64_t *n, int32_t *fuse_steps, int32_t *ring_levels);
+
+/* Copy the delay array (int8[nsteps_max][F], after the clamp) to host memory.
+ * Synchronous. */
+at_status at_delays_copy(const at_ctx *ctx, int8_t *host_out);
+
+/* Snapshot / restore of the full stepper state (the field u at the current
+ * step, the ring and n).  at_snapshot_bytes gives the device buffer size. */
+at_status at_snapshot_bytes(const at_ctx *ctx, uint64_t *bytes);
+at_status at_snapshot(at_ctx *ctx, const double *u, void *dev_buf);
+at_status at_restore(at_ctx *ctx, const void *dev_buf, double *u);
+
+/* Reductions over a field of the context's size, written to device memory:
+ * out3[0] = max |u|, out3[1] = mean u, out3[2] = sum |u| (wave64 shuffles,
+ * compensated per-workgroup partials, fixed-order final pass). */
+at_status at_stats(at_ctx *ctx, const double *u, double *out3);
+
+/* Final-time misfit J = 0.5 * sum (u - target)^2 into *J_dev, and
+ * lambda = u - target (= dJ/du) into lam (may be NULL). */
+at_status at_loss(at_ctx *ctx, const double *u, const double *target, double *lam,
+                  double *J_dev);
+
+/* Discrete adjoint of the recorded run (record mode, 1D): given
+ * lambda_T = dJ/du at the current step n_end (run from n = 0), writes
+ * dJ/du0 into grad_u0 and dJ/dnu into *grad_nu_dev (dt held fixed).  Replays
+ * the same delays; recomputes each checkpoint segment of ckpt_every steps in
+ * reverse order.  The context stays at n_end. */
+at_status at_adjoint(at_ctx *ctx, const double *lambda_T, double *grad_u0, double *grad_nu_dev);
+
+/* ---------------------------------------------------------------------- */
+/* Batched form: many independent 1D instances of uneven size advanced by */
+/* the same launches.                                                      */
+/* ---------------------------------------------------------------------- */
+typedef struct at_batch at_batch;
+
+/* cfgs[0..count-1] are 1D configurations (record = 0) that all share one
+ * order and one stream (the first one's).  Each instance's workspace fields
+ * are ignored; the batch uses the single workspace given here, of at least
+ * at_batch_workspace_bytes() bytes. */
+at_status at_batch_workspace_bytes(const at_config *cfgs, int32_t count, uint64_t *bytes);
+at_status at_batch_init(const at_config *cfgs, int32_t count, void *workspace,
+                        uint64_t workspace_bytes, at_batch **out);
+void at_batch_free(at_batch *b);
+
+/* Advance every instance by nsteps; u_dev[j] / scratch_dev[j] are host
+ * arrays of device pointers for instance j; results are left in u_dev[j].
+ * use_graph = 1 captures the launch sequence in a HIP graph and replays it. */
+at_status at_batch_run(at_batch *b, double *const *u_dev, double *const *scratch_dev,
+                       int64_t nsteps, int32_t use_graph);
+
+/* Choose the batch's steps per launch by timing (same contract as
+ * at_autotune, per batch). */
+at_status at_batch_autotune(at_batch *b, double *const *u_dev, double *const *t1,
+                            double *const *t2, int32_t trial_steps, int32_t *chosen);
+at_status at_batch_set_fuse(at_batch *b, int32_t fuse_steps);
+at_status at_set_fuse(at_ctx *ctx, int32_t fuse_steps);
+
+/* Thread-local message of the last failure in this thread ("" if none). */
+const char *at_last_error(void);
+
+/* AT_ABI_VERSION of the loaded library. */
+int32_t at_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AT_H */

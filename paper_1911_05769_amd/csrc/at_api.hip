@@ -1,0 +1,580 @@
+// Host side of libat.so: configuration checks, workspace layout, delay set-up,
+// launch sequencing (plain, fused, recorded), checkpoints, adjoint sweep,
+// snapshots, reductions and the autotuner.  See include/at.h for the contract.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/at.h"
+#include "at_internal.h"
+
+using namespace atk;
+
+// 3D hooks (defined in at_step3d.hip)
+at_status at3_check(const at_config *c);
+uint64_t at3_ring_level_doubles(const at_config *c);
+
+namespace {
+
+thread_local std::string g_err;
+
+at_status fail(at_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define AT_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(AT_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    uint64_t delays = 0, ring = 0, red = 0, ckpt = 0, seg = 0, lam = 0, mu = 0, gnu = 0, total = 0;
+    int64_t nckpt = 0, ngnu = 0;
+    int R = 0, Rmu = 0;
+};
+
+struct Derived {
+    int dim, order, h, m;
+    int64_t N;      // total points
+    int64_t F;      // faces
+    int64_t nb;     // tiles / blocks
+    int64_t P, W;   // 1D
+    double c1[3], c2[3];
+};
+
+at_status derive(const at_config *c, Derived &d)
+{
+    if (!c) return fail(AT_ERR_ARG, "null configuration");
+    if (c->abi_version != AT_ABI_VERSION)
+        return fail(AT_ERR_ARG, "abi_version %d, library has %d", c->abi_version, AT_ABI_VERSION);
+    if (c->dim != 1 && c->dim != 3) return fail(AT_ERR_ARG, "dim must be 1 or 3");
+    if (c->order != 2 && c->order != 4) return fail(AT_ERR_ARG, "order must be 2 or 4");
+    if (c->dim == 3 && c->order != 2) return fail(AT_ERR_ARG, "3D stepper is order 2");
+    if (c->L < 0 || c->L > 15) return fail(AT_ERR_ARG, "L must be in 0..15");
+    if (c->halo_mode != 0 && c->halo_mode != 1) return fail(AT_ERR_ARG, "halo_mode must be 0 or 1");
+    if (c->adv_mode != 0 && c->adv_mode != 1) return fail(AT_ERR_ARG, "adv_mode must be 0 or 1");
+    if (c->adv_mode == 1 && c->dim != 1) return fail(AT_ERR_ARG, "linear advection is 1D only");
+    if (!(c->nu >= 0.0) || !isfinite(c->nu)) return fail(AT_ERR_ARG, "nu must be finite and >= 0");
+    if (!(c->dt > 0.0) || !isfinite(c->dt)) return fail(AT_ERR_ARG, "dt must be finite and > 0");
+    if (!(c->length > 0.0) || !isfinite(c->length)) return fail(AT_ERR_ARG, "length must be > 0");
+    if (c->nsteps_max < 0) return fail(AT_ERR_ARG, "nsteps_max must be >= 0");
+    if (c->delay_mode != AT_DELAY_GENERATE && c->delay_mode != AT_DELAY_HOST)
+        return fail(AT_ERR_ARG, "unknown delay_mode");
+    if (c->delay_mode == AT_DELAY_GENERATE && c->delay_dist != AT_DIST_UNIFORM &&
+        c->delay_dist != AT_DIST_HALF_ZERO)
+        return fail(AT_ERR_ARG, "unknown delay_dist");
+    if (c->delay_mode == AT_DELAY_HOST && !c->delays_host && c->nsteps_max > 0)
+        return fail(AT_ERR_ARG, "delays_host is NULL");
+    if (c->fuse_steps < 0 || c->fuse_steps > kMaxFuse)
+        return fail(AT_ERR_ARG, "fuse_steps must be in 0..%d", kMaxFuse);
+    if (c->record) {
+        if (c->dim != 1) return fail(AT_ERR_ARG, "record mode (adjoint) is 1D only");
+        if (c->ckpt_every < 1) return fail(AT_ERR_ARG, "record mode needs ckpt_every >= 1");
+    }
+    d.dim = c->dim;
+    d.order = c->order;
+    d.h = c->order / 2;
+    d.m = (c->order == 2) ? 2 : 3;
+    const int naxes = c->dim;
+    d.N = 1;
+    d.nb = 1;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t n = c->n[a];
+        const int64_t p = c->p[a];
+        if (a >= naxes) {
+            if (n != 1 || p != 1) return fail(AT_ERR_SHAPE, "unused axis %d must have n = p = 1", a);
+            d.c1[a] = d.c2[a] = 0.0;
+            continue;
+        }
+        if (n <= 0 || p <= 0) return fail(AT_ERR_SHAPE, "axis %d: n and p must be positive", a);
+        if (n % p != 0) return fail(AT_ERR_SHAPE, "axis %d: n %% p != 0", a);
+        if (n / p < 2 * d.h) return fail(AT_ERR_SHAPE, "axis %d: tile width %lld < 2h", a,
+                                         (long long)(n / p));
+        const double dx = c->length / (double)n;
+        if (c->order == 2) { d.c1[a] = 1.0 / (2.0 * dx); d.c2[a] = 1.0 / (dx * dx); }
+        else { d.c1[a] = 1.0 / (12.0 * dx); d.c2[a] = 1.0 / (12.0 * (dx * dx)); }
+        d.N *= n;
+        d.nb *= p;
+    }
+    d.F = (c->dim == 1 ? 2 : 6) * d.nb;
+    d.P = c->p[0];
+    d.W = c->n[0] / c->p[0];
+    if (d.N > ((int64_t)1 << 40)) return fail(AT_ERR_SHAPE, "grid too large");
+    if (c->dim == 3) {
+        at_status st = at3_check(c);
+        if (st != AT_OK) return st;
+    }
+    return AT_OK;
+}
+
+// ring levels: L+m-1 past levels are read while up to kMaxFuse are written;
+// record mode keeps every level of the run (the adjoint re-reads them).
+int ring_levels(const at_config *c, const Derived &d)
+{
+    int64_t R = c->L + d.m - 1 + kMaxFuse;
+    if (c->record) R = std::max<int64_t>(R, c->nsteps_max + 1);
+    return (int)R;
+}
+
+}  // namespace
+
+struct at_ctx {
+    at_config cfg;
+    Derived d;
+    Layout lay;
+    hipStream_t st;
+    int8_t *delays;
+    double *ring, *red, *ckpt, *seg, *lam, *mu, *gnu;
+    int64_t n;
+    int fuse;
+};
+
+namespace {
+
+uint64_t ring_level_doubles(const at_config *c, const Derived &d)
+{
+    if (d.dim == 1) return (uint64_t)d.P * 2 * d.h;
+    return at3_ring_level_doubles(c);
+}
+
+int64_t adj_blocks(const Derived &d)
+{
+    const int64_t per = adj1d_points_per_block();
+    return (d.N + per - 1) / per;
+}
+
+at_status make_layout(const at_config *c, const Derived &d, Layout &L)
+{
+    L.R = ring_levels(c, d);
+    L.Rmu = c->L + d.m;
+    uint64_t off = 0;
+    L.delays = off;
+    off = align_up(off + (uint64_t)c->nsteps_max * (uint64_t)d.F);
+    L.ring = off;
+    off = align_up(off + 8ull * (uint64_t)L.R * ring_level_doubles(c, d));
+    L.red = off;
+    off = align_up(off + 8ull * (kRedBlocks * 5 + 16));
+    if (c->record) {
+        L.nckpt = c->nsteps_max / c->ckpt_every + 1;
+        L.ckpt = off;
+        off = align_up(off + 8ull * (uint64_t)L.nckpt * (uint64_t)d.N);
+        L.seg = off;
+        off = align_up(off + 8ull * (uint64_t)c->ckpt_every * (uint64_t)d.N);
+        L.lam = off;
+        off = align_up(off + 8ull * 2 * (uint64_t)d.N);
+        L.mu = off;
+        off = align_up(off + 8ull * (uint64_t)L.Rmu * (uint64_t)d.P * 2 * d.h);
+        L.ngnu = adj_blocks(d);
+        L.gnu = off;
+        off = align_up(off + 8ull * 2 * (uint64_t)L.ngnu);
+    }
+    L.total = off;
+    return AT_OK;
+}
+
+// Largest steps-per-launch usable for this 1D configuration.
+int max_fuse_1d(const Derived &d)
+{
+    const int reg = kThreads * step1d_points_per_thread();
+    int best = 1;
+    for (int s = 1; s <= kMaxFuse; ++s) {
+        if (reg - 2 * s * d.h < std::min<int64_t>(reg / 2, d.N) && s > 1) break;
+        const int NT = (int)((reg - 1) / d.W + 2);
+        if (step1d_lds_bytes(d.order, s, NT) > 64 * 1024) break;
+        best = s;
+    }
+    return best;
+}
+
+at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int s, int publish)
+{
+    const Derived &d = c->d;
+    const int reg = kThreads * step1d_points_per_thread();
+    Step1D a;
+    a.uin = uin;
+    a.uout = uout;
+    a.ring = c->ring;
+    a.delays = c->delays;
+    a.N = d.N;
+    a.P = d.P;
+    a.W = d.W;
+    a.n0 = n0;
+    a.CH = std::min<int64_t>(reg - 2 * s * d.h, d.N);
+    if (a.CH < 1) return fail(AT_ERR_ARG, "fuse_steps %d too large for this stencil", s);
+    a.s = s;
+    a.R = c->lay.R;
+    a.NT = (int)((reg - 1) / d.W + 2);
+    a.stale = c->cfg.halo_mode;
+    a.publish = publish;
+    a.pad0 = 0;
+    a.nu = c->cfg.nu;
+    a.dt = c->cfg.dt;
+    a.c1 = d.c1[0];
+    a.c2 = d.c2[0];
+    a.cadv = c->cfg.adv_speed;
+    const int64_t nblocks = (d.N + a.CH - 1) / a.CH;
+    AT_HIP(launch_step1d(a, d.order, c->cfg.adv_mode == 1, nblocks, c->st));
+    return AT_OK;
+}
+
+}  // namespace
+
+// 3D launcher (at_step3d.hip)
+at_status at3_launch(at_ctx *c, const double *uin, double *uout, int64_t n0, int s, int publish);
+int at3_max_fuse(const at_ctx *c);
+
+// accessors used by the 3D translation unit
+extern "C++" {
+const at_config *at_ctx_cfg(const at_ctx *c) { return &c->cfg; }
+double *at_ctx_ring(const at_ctx *c) { return c->ring; }
+const int8_t *at_ctx_delays(const at_ctx *c) { return c->delays; }
+int at_ctx_R(const at_ctx *c) { return c->lay.R; }
+hipStream_t at_ctx_stream(const at_ctx *c) { return c->st; }
+void at_ctx_coefs(const at_ctx *c, double *c1, double *c2)
+{
+    for (int a = 0; a < 3; ++a) { c1[a] = c->d.c1[a]; c2[a] = c->d.c2[a]; }
+}
+at_status at_fail(at_status st, const char *msg) { return fail(st, "%s", msg); }
+}
+
+namespace {
+
+at_status launch_any(at_ctx *c, const double *uin, double *uout, int64_t n0, int s, int publish)
+{
+    if (c->d.dim == 1) return launch_1d(c, uin, uout, n0, s, publish);
+    return at3_launch(c, uin, uout, n0, s, publish);
+}
+
+int max_fuse(const at_ctx *c)
+{
+    return c->d.dim == 1 ? max_fuse_1d(c->d) : at3_max_fuse(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t at_abi_version(void) { return AT_ABI_VERSION; }
+
+const char *at_last_error(void) { return g_err.c_str(); }
+
+uint64_t at_config_bytes(void) { return sizeof(at_config); }
+
+at_status at_workspace_bytes(const at_config *cfg, uint64_t *bytes)
+{
+    Derived d;
+    at_status st = derive(cfg, d);
+    if (st) return st;
+    if (!bytes) return fail(AT_ERR_ARG, "null output");
+    Layout L;
+    make_layout(cfg, d, L);
+    *bytes = L.total;
+    return AT_OK;
+}
+
+at_status at_init(const at_config *cfg, at_ctx **out)
+{
+    if (!out) return fail(AT_ERR_ARG, "null output");
+    *out = nullptr;
+    Derived d;
+    at_status st = derive(cfg, d);
+    if (st) return st;
+    Layout L;
+    make_layout(cfg, d, L);
+    if (!cfg->workspace) return fail(AT_ERR_ARG, "workspace is NULL");
+    if (((uintptr_t)cfg->workspace) % kAlign) return fail(AT_ERR_ARG, "workspace not 256-byte aligned");
+    if (cfg->workspace_bytes < L.total)
+        return fail(AT_ERR_NOMEM, "workspace %llu bytes, need %llu",
+                    (unsigned long long)cfg->workspace_bytes, (unsigned long long)L.total);
+    if (cfg->delay_mode == AT_DELAY_HOST) {
+        // every entry must satisfy 0 <= k <= min(L, max(0, n - m + 1))
+        for (int64_t n = 0; n < cfg->nsteps_max; ++n) {
+            int64_t lim = std::min<int64_t>(cfg->L, std::max<int64_t>(0, n - d.m + 1));
+            const int8_t *row = cfg->delays_host + n * d.F;
+            for (int64_t f = 0; f < d.F; ++f)
+                if (row[f] < 0 || row[f] > lim)
+                    return fail(AT_ERR_DELAY, "delay k[%lld][%lld] = %d outside 0..%lld",
+                                (long long)n, (long long)f, (int)row[f], (long long)lim);
+        }
+    }
+    at_ctx *c = new (std::nothrow) at_ctx;
+    if (!c) return fail(AT_ERR_NOMEM, "host allocation failed");
+    c->cfg = *cfg;
+    c->cfg.delays_host = nullptr;
+    c->d = d;
+    c->lay = L;
+    c->st = (hipStream_t)cfg->stream;
+    char *base = (char *)cfg->workspace;
+    c->delays = (int8_t *)(base + L.delays);
+    c->ring = (double *)(base + L.ring);
+    c->red = (double *)(base + L.red);
+    c->ckpt = cfg->record ? (double *)(base + L.ckpt) : nullptr;
+    c->seg = cfg->record ? (double *)(base + L.seg) : nullptr;
+    c->lam = cfg->record ? (double *)(base + L.lam) : nullptr;
+    c->mu = cfg->record ? (double *)(base + L.mu) : nullptr;
+    c->gnu = cfg->record ? (double *)(base + L.gnu) : nullptr;
+    c->n = 0;
+    c->fuse = cfg->fuse_steps > 0 ? std::min(cfg->fuse_steps, max_fuse(c)) : 1;
+    hipError_t e = hipSuccess;
+    if (cfg->delay_mode == AT_DELAY_GENERATE)
+        e = launch_delays(c->delays, cfg->nsteps_max, d.F, cfg->L, d.m, cfg->delay_dist,
+                          cfg->delay_seed, c->st);
+    else if (cfg->nsteps_max > 0)
+        e = hipMemcpyAsync(c->delays, cfg->delays_host, (size_t)(cfg->nsteps_max * d.F),
+                           hipMemcpyHostToDevice, c->st);
+    if (e == hipSuccess)
+        e = launch_fill(c->ring, (int64_t)L.R * (int64_t)ring_level_doubles(cfg, d), 0.0, c->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(AT_ERR_HIP, "at_init: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return AT_OK;
+}
+
+void at_free(at_ctx *c) { delete c; }
+
+at_status at_set_fuse(at_ctx *c, int32_t s)
+{
+    if (!c) return fail(AT_ERR_ARG, "null context");
+    if (s < 1 || s > kMaxFuse) return fail(AT_ERR_ARG, "fuse_steps must be in 1..%d", kMaxFuse);
+    const int mf = max_fuse(c);
+    if (s > mf) return fail(AT_ERR_ARG, "fuse_steps %d exceeds the limit %d of this grid", s, mf);
+    c->fuse = s;
+    return AT_OK;
+}
+
+at_status at_query(const at_ctx *c, int64_t *n, int32_t *fuse, int32_t *R)
+{
+    if (!c) return fail(AT_ERR_ARG, "null context");
+    if (n) *n = c->n;
+    if (fuse) *fuse = c->fuse;
+    if (R) *R = c->lay.R;
+    return AT_OK;
+}
+
+at_status at_step(at_ctx *c, const double *u_in, double *u_out)
+{
+    if (!c || !u_in || !u_out) return fail(AT_ERR_ARG, "null argument");
+    if (u_in == u_out) return fail(AT_ERR_ARG, "u_in and u_out must differ");
+    if (c->n + 1 > c->cfg.nsteps_max) return fail(AT_ERR_STATE, "step %lld beyond nsteps_max",
+                                                  (long long)c->n);
+    if (c->cfg.record && c->n % c->cfg.ckpt_every == 0)
+        AT_HIP(launch_copy(c->ckpt + (c->n / c->cfg.ckpt_every) * c->d.N, u_in, c->d.N, c->st));
+    at_status st = launch_any(c, u_in, u_out, c->n, 1, 1);
+    if (st) return st;
+    c->n += 1;
+    return AT_OK;
+}
+
+at_status at_run(at_ctx *c, double *u, double *scratch, int64_t nsteps)
+{
+    if (!c || !u || !scratch) return fail(AT_ERR_ARG, "null argument");
+    if (u == scratch) return fail(AT_ERR_ARG, "u and scratch must differ");
+    if (nsteps < 0) return fail(AT_ERR_ARG, "nsteps < 0");
+    if (c->n + nsteps > c->cfg.nsteps_max)
+        return fail(AT_ERR_STATE, "run to step %lld beyond nsteps_max %lld",
+                    (long long)(c->n + nsteps), (long long)c->cfg.nsteps_max);
+    double *cur = u, *oth = scratch;
+    int64_t left = nsteps;
+    const int64_t C = c->cfg.ckpt_every;
+    while (left > 0) {
+        int64_t s = std::min<int64_t>(c->fuse, left);
+        if (c->cfg.record) {
+            if (c->n % C == 0)
+                AT_HIP(launch_copy(c->ckpt + (c->n / C) * c->d.N, cur, c->d.N, c->st));
+            s = std::min<int64_t>(s, C - c->n % C);
+        }
+        at_status st = launch_any(c, cur, oth, c->n, (int)s, 1);
+        if (st) return st;
+        std::swap(cur, oth);
+        c->n += s;
+        left -= s;
+    }
+    if (cur != u) AT_HIP(launch_copy(u, cur, c->d.N, c->st));
+    return AT_OK;
+}
+
+at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32_t trial_steps,
+                      int32_t *chosen)
+{
+    if (!c || !u0 || !t1 || !t2) return fail(AT_ERR_ARG, "null argument");
+    if (c->n != 0) return fail(AT_ERR_STATE, "autotune needs a context at step 0");
+    if (c->cfg.record) return fail(AT_ERR_STATE, "autotune is not available in record mode");
+    if (trial_steps < 1 || trial_steps > c->cfg.nsteps_max)
+        return fail(AT_ERR_ARG, "trial_steps must be in 1..nsteps_max");
+    const int mf = max_fuse(c);
+    static const int cands[] = {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32};
+    hipEvent_t e0, e1;
+    AT_HIP(hipEventCreate(&e0));
+    AT_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int best = 1;
+    const uint64_t rlev = ring_level_doubles(&c->cfg, c->d);
+    for (int s : cands) {
+        if (s > mf) break;
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            AT_HIP(launch_fill(c->ring, (int64_t)c->lay.R * (int64_t)rlev, 0.0, c->st));
+            AT_HIP(launch_copy(t1, u0, c->d.N, c->st));
+            c->n = 0;
+            c->fuse = s;
+            AT_HIP(hipEventRecord(e0, c->st));
+            at_status st = at_run(c, t1, t2, trial_steps);
+            if (st) { c->n = 0; return st; }
+            AT_HIP(hipEventRecord(e1, c->st));
+            AT_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            AT_HIP(hipEventElapsedTime(&ms, e0, e1));
+            ms_best = std::min(ms_best, ms);
+        }
+        if (ms_best < best_ms * 0.98f) { best_ms = ms_best; best = s; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    AT_HIP(launch_fill(c->ring, (int64_t)c->lay.R * (int64_t)rlev, 0.0, c->st));
+    AT_HIP(hipStreamSynchronize(c->st));
+    c->n = 0;
+    c->fuse = best;
+    if (chosen) *chosen = best;
+    return AT_OK;
+}
+
+at_status at_delays_copy(const at_ctx *c, int8_t *host_out)
+{
+    if (!c || !host_out) return fail(AT_ERR_ARG, "null argument");
+    AT_HIP(hipMemcpyAsync(host_out, c->delays, (size_t)(c->cfg.nsteps_max * c->d.F),
+                          hipMemcpyDeviceToHost, c->st));
+    AT_HIP(hipStreamSynchronize(c->st));
+    return AT_OK;
+}
+
+at_status at_snapshot_bytes(const at_ctx *c, uint64_t *bytes)
+{
+    if (!c || !bytes) return fail(AT_ERR_ARG, "null argument");
+    const uint64_t comps = c->d.dim == 1 ? 1 : 3;
+    *bytes = align_up(8ull * comps * c->d.N) +
+             align_up(8ull * c->lay.R * ring_level_doubles(&c->cfg, c->d)) + kAlign;
+    return AT_OK;
+}
+
+at_status at_snapshot(at_ctx *c, const double *u, void *dev_buf)
+{
+    if (!c || !u || !dev_buf) return fail(AT_ERR_ARG, "null argument");
+    const uint64_t comps = c->d.dim == 1 ? 1 : 3;
+    const uint64_t nu = comps * c->d.N, nr = (uint64_t)c->lay.R * ring_level_doubles(&c->cfg, c->d);
+    char *b = (char *)dev_buf;
+    AT_HIP(launch_copy((double *)b, u, nu, c->st));
+    AT_HIP(launch_copy((double *)(b + align_up(8 * nu)), c->ring, nr, c->st));
+    double nn = (double)c->n;   // step counter, exact below 2^53
+    AT_HIP(hipMemcpyAsync(b + align_up(8 * nu) + align_up(8 * nr), &nn, sizeof nn,
+                          hipMemcpyHostToDevice, c->st));
+    AT_HIP(hipStreamSynchronize(c->st));
+    return AT_OK;
+}
+
+at_status at_restore(at_ctx *c, const void *dev_buf, double *u)
+{
+    if (!c || !u || !dev_buf) return fail(AT_ERR_ARG, "null argument");
+    const uint64_t comps = c->d.dim == 1 ? 1 : 3;
+    const uint64_t nu = comps * c->d.N, nr = (uint64_t)c->lay.R * ring_level_doubles(&c->cfg, c->d);
+    const char *b = (const char *)dev_buf;
+    double nn = 0.0;
+    AT_HIP(hipMemcpyAsync(&nn, b + align_up(8 * nu) + align_up(8 * nr), sizeof nn,
+                          hipMemcpyDeviceToHost, c->st));
+    AT_HIP(hipStreamSynchronize(c->st));
+    if (!(nn >= 0.0) || nn > (double)c->cfg.nsteps_max || nn != floor(nn))
+        return fail(AT_ERR_ARG, "buffer does not hold a snapshot of this context");
+    AT_HIP(launch_copy(u, (const double *)b, nu, c->st));
+    AT_HIP(launch_copy(c->ring, (const double *)(b + align_up(8 * nu)), nr, c->st));
+    c->n = (int64_t)nn;
+    return AT_OK;
+}
+
+at_status at_stats(at_ctx *c, const double *u, double *out3)
+{
+    if (!c || !u || !out3) return fail(AT_ERR_ARG, "null argument");
+    const int64_t n = (c->d.dim == 1 ? 1 : 3) * c->d.N;
+    AT_HIP(launch_stats(u, n, c->red, out3, c->st));
+    return AT_OK;
+}
+
+at_status at_loss(at_ctx *c, const double *u, const double *target, double *lam, double *J_dev)
+{
+    if (!c || !u || !target || !J_dev) return fail(AT_ERR_ARG, "null argument");
+    const int64_t n = (c->d.dim == 1 ? 1 : 3) * c->d.N;
+    AT_HIP(launch_loss(u, target, lam, n, c->red, J_dev, c->st));
+    return AT_OK;
+}
+
+at_status at_adjoint(at_ctx *c, const double *lambda_T, double *grad_u0, double *grad_nu_dev)
+{
+    if (!c || !lambda_T || !grad_u0 || !grad_nu_dev) return fail(AT_ERR_ARG, "null argument");
+    if (!c->cfg.record) return fail(AT_ERR_STATE, "at_adjoint needs a context in record mode");
+    const Derived &d = c->d;
+    const int64_t nend = c->n, C = c->cfg.ckpt_every, N = d.N;
+    double *lcur = c->lam, *loth = c->lam + N;
+    AT_HIP(launch_copy(lcur, lambda_T, N, c->st));
+    AT_HIP(launch_fill(c->mu, (int64_t)c->lay.Rmu * d.P * 2 * d.h, 0.0, c->st));
+    AT_HIP(launch_fill(c->gnu, 2 * c->lay.ngnu, 0.0, c->st));
+    if (nend > 0) {
+        for (int64_t a0 = ((nend - 1) / C) * C; a0 >= 0; a0 -= C) {
+            const int64_t a1 = std::min(a0 + C, nend);
+            AT_HIP(launch_copy(c->seg, c->ckpt + (a0 / C) * N, N, c->st));
+            for (int64_t n = a0; n + 1 < a1; ++n) {
+                at_status st = launch_1d(c, c->seg + (n - a0) * N, c->seg + (n + 1 - a0) * N, n, 1, 0);
+                if (st) return st;
+            }
+            for (int64_t n = a1 - 1; n >= a0; --n) {
+                Adj1D a;
+                a.lam_in = lcur;
+                a.lam_out = loth;
+                a.u = c->seg + (n - a0) * N;
+                a.ring = c->ring;
+                a.mu = c->mu;
+                a.delays = c->delays;
+                a.gnu = c->gnu;
+                a.N = N;
+                a.P = d.P;
+                a.W = d.W;
+                a.n = n;
+                a.nsteps_total = nend;
+                a.R = c->lay.R;
+                a.Rmu = c->lay.Rmu;
+                a.L = c->cfg.L;
+                a.stale = c->cfg.halo_mode;
+                a.nu = c->cfg.nu;
+                a.dt = c->cfg.dt;
+                a.c1 = d.c1[0];
+                a.c2 = d.c2[0];
+                a.cadv = c->cfg.adv_speed;
+                AT_HIP(launch_adj1d(a, d.order, c->cfg.adv_mode == 1, c->lay.ngnu, c->st));
+                std::swap(lcur, loth);
+            }
+        }
+    }
+    AT_HIP(launch_copy(grad_u0, lcur, N, c->st));
+    AT_HIP(launch_gnu_final(c->gnu, c->lay.ngnu, grad_nu_dev, c->st));
+    return AT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+// Internal declarations shared by the kernel and host translation units of
+// libat.so.  Not part of the ABI (see include/at.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace atk {
+
+constexpr int kThreads = 256;     // workgroup size of every stencil kernel (4 wave64)
+constexpr int kMaxFuse = 32;      // largest steps-per-launch the ring is sized for
+constexpr int kRedBlocks = 1024;  // workgroups of the first reduction pass
+
+// Arguments of one launch of the 1D stepper: s steps n0 .. n0+s-1.
+struct Step1D {
+    const double *uin;        // level n0, double[N]
+    double *uout;             // level n0+s, double[N]
+    double *ring;             // edge levels: [R][P][2][h]
+    const int8_t *delays;     // k[n][2P]
+    int64_t N, P, W;
+    int64_t n0;
+    int64_t CH;               // points owned by one workgroup
+    int32_t s;                // steps in this launch
+    int32_t R;                // ring levels
+    int32_t NT;               // region-local tile slots in the LDS edge history
+    int32_t stale;            // 1: halo = level n-k without extrapolation
+    int32_t publish;          // 1: write level n edges to the ring
+    int32_t pad0;
+    double nu, dt, c1, c2, cadv;
+};
+
+// Reverse (adjoint) step at level n of the 1D stepper.
+struct Adj1D {
+    const double *lam_in;     // lambda^{n+1}
+    double *lam_out;          // lambda^n
+    const double *u;          // u^n
+    const double *ring;       // full edge history (record mode): [R][P][2][h]
+    double *mu;               // halo adjoints: [Rmu][P][2][h]
+    const int8_t *delays;     // k[n][2P]
+    double *gnu;              // per-workgroup compensated dJ/dnu: [nblocks][2]
+    int64_t N, P, W;
+    int64_t n;
+    int64_t nsteps_total;     // steps of the recorded run (gather window bound)
+    int32_t R, Rmu, L, stale;
+    double nu, dt, c1, c2, cadv;
+};
+
+// Neumaier-compensated accumulator used by the reductions.
+struct Acc {
+    double s, c;
+};
+
+__device__ __forceinline__ void acc_add(Acc &a, double x)
+{
+    const double t = a.s + x;
+    if (fabs(a.s) >= fabs(x)) a.c += (a.s - t) + x;
+    else a.c += (x - t) + a.s;
+    a.s = t;
+}
+
+__device__ __forceinline__ void acc_merge(Acc &a, const Acc &b)
+{
+    acc_add(a, b.s);
+    a.c += b.c;
+}
+
+__device__ __forceinline__ Acc wave_acc(Acc a)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        Acc b;
+        b.s = __shfl_down(a.s, off, 64);
+        b.c = __shfl_down(a.c, off, 64);
+        acc_merge(a, b);
+    }
+    return a;
+}
+
+// Launchers (defined in the .hip files); return hipError_t of the launch.
+hipError_t launch_delays(int8_t *out, int64_t nsteps, int64_t F, int L, int m, int dist,
+                         uint64_t seed, hipStream_t st);
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
+hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
+size_t step1d_lds_bytes(int order, int s, int NT);
+int step1d_points_per_thread();
+hipError_t launch_step1d(const Step1D &a, int order, bool linear, int64_t nblocks,
+                         hipStream_t st);
+hipError_t launch_adj1d(const Adj1D &a, int order, bool linear, int64_t nblocks,
+                        hipStream_t st);
+int adj1d_points_per_block();
+hipError_t launch_gnu_final(const double *part, int64_t nparts, double *out, hipStream_t st);
+hipError_t launch_stats(const double *u, int64_t n, double *part, double *out3, hipStream_t st);
+hipError_t launch_loss(const double *u, const double *t, double *lam, int64_t n, double *part,
+                       double *J, hipStream_t st);
+
+}  // namespace atk

@@ -1,0 +1,455 @@
+// 1D kernels of libat.so for gfx950: delay generator, AT stepper (one or
+// several fused steps per launch), fills/copies and reductions.
+//
+// Method: viscous Burgers u_t + u u_x = nu u_xx (or linear advection c u_x),
+// central differences and forward Euler (paper section 3.2) on P tiles of a
+// periodic grid.  A point whose stencil crosses its tile's edge reads a halo
+// value extrapolated in time from the neighbour edge's levels n-k, n-k-1, ...
+// (section 2, Eqs. (1)-(2); three levels for the 4th-order scheme), with the
+// delay k prescribed per directed face and step.  As in section 5.2, the halo
+// approximation is separate from the stencil, which is the same everywhere.
+//
+// Arithmetic is binary64 with contraction disabled (-ffp-contract=off); the
+// evaluation order of every formula is fixed:
+//   order 2: D1 = (r1 - l1)*c1,                 D2 = ((r1 - 2u) + l1)*c2
+//   order 4: D1 = (8(r1 - l1) - (r2 - l2))*c1,  D2 = ((16(r1 + l1) - 30u) - (r2 + l2))*c2
+//   F = nu*D2 - a*D1 (a = u, or c for linear advection),  u' = u + dt*F
+//   halo, two levels:   H = v0 + k*(v0 - v1)
+//   halo, three levels: H = (v0 + k*d1) + w2*(d1 - (v1 - v2)), d1 = v0 - v1, w2 = 0.5*k*(k+1)
+//
+// Work decomposition of k_step1d (s steps per launch):
+//   * a workgroup of 256 threads owns CH consecutive points and loads the
+//     region [c0 - s*h, c0 + CH + s*h) of level n0 (coalesced, through LDS);
+//   * each thread keeps PPT consecutive region points in registers and trades
+//     h values per side with its neighbours through LDS once per step;
+//   * the valid part of the region shrinks by h per step (overlapped
+//     trapezoids); neighbouring tiles' edges inside the region are recomputed
+//     redundantly with the same operations, so the result is bit-identical to
+//     one launch per step;
+//   * edge values of in-launch levels are kept in an LDS edge history for
+//     delayed halo reads; levels before n0 come from the ring in HBM;
+//   * every owned tile-edge point of level n is published to ring slot n mod R.
+#include "at_internal.h"
+
+namespace atk {
+
+namespace {
+
+constexpr int kPPT = 16;   // region points per thread
+
+__device__ __forceinline__ int64_t floordiv(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+__device__ __forceinline__ double extrap(int kk, bool stale, double v0, double v1, double v2,
+                                         int M)
+{
+    if (stale) return v0;
+    const double dk = (double)kk;
+    const double d1 = v0 - v1;
+    if (M == 2) return v0 + dk * d1;
+    const double w2 = 0.5 * dk * (dk + 1.0);
+    return (v0 + dk * d1) + w2 * (d1 - (v1 - v2));
+}
+
+template <int ORDER, bool LINEAR>
+__device__ __forceinline__ double update(const double *nb, double u, const Step1D &a)
+{
+    double D1, D2;
+    if constexpr (ORDER == 2) {
+        const double l1 = nb[0], r1 = nb[1];
+        D1 = (r1 - l1) * a.c1;
+        D2 = ((r1 - 2.0 * u) + l1) * a.c2;
+    } else {
+        const double l2 = nb[0], l1 = nb[1], r1 = nb[2], r2 = nb[3];
+        D1 = (8.0 * (r1 - l1) - (r2 - l2)) * a.c1;
+        D2 = ((16.0 * (r1 + l1) - 30.0 * u) - (r2 + l2)) * a.c2;
+    }
+    const double adv = LINEAR ? a.cadv : u;
+    const double F = a.nu * D2 - adv * D1;
+    return u + a.dt * F;
+}
+
+template <int ORDER, bool LINEAR>
+__global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
+{
+    constexpr int H = ORDER / 2;
+    constexpr int M = (ORDER == 2) ? 2 : 3;
+    constexpr int PPT = kPPT;
+    extern __shared__ double lds[];
+    double *stage = lds;                                  // [kThreads*PPT + kThreads]
+    double *xch = lds;                                    // [2][kThreads][2H]  (aliases stage)
+    double *eh = lds + 2 * kThreads * 2 * H;              // [s-1][NT][2][H]    (aliases stage)
+
+    const int tid = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * a.CH;
+    const int64_t owned = (a.N - c0 < a.CH) ? (a.N - c0) : a.CH;
+    const int sh = a.s * H;
+    const int E = (int)owned + 2 * sh;                    // region length (<= kThreads*PPT)
+    const int64_t G0 = c0 - sh;                           // unwrapped start (may be < 0)
+    int64_t G0w = G0 % a.N;
+    if (G0w < 0) G0w += a.N;
+
+    // ---- level n0 of the region: coalesced loads -> LDS -> registers
+#pragma unroll
+    for (int it = 0; it < PPT; ++it) {
+        const int r = it * kThreads + tid;
+        double v = 0.0;
+        if (r < E) {
+            int64_t g = G0w + r;
+            while (g >= a.N) g -= a.N;
+            v = a.uin[g];
+        }
+        stage[r + r / PPT] = v;
+    }
+    __syncthreads();
+    double w[PPT + 2 * H];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) w[H + j] = stage[tid * PPT + j + tid];
+#pragma unroll
+    for (int q = 0; q < H; ++q) { w[q] = 0.0; w[PPT + H + q] = 0.0; }
+    __syncthreads();
+
+    // ---- tile bookkeeping of this thread's first point
+    const int rp0 = tid * PPT;                            // region position of point 0
+    const int64_t Gt = G0 + rp0;
+    const int64_t tdiv = floordiv(Gt, a.W);
+    const int64_t o0 = Gt - tdiv * a.W;                   // offset in its tile, [0, W)
+    const int tl0 = (int)(tdiv - floordiv(G0, a.W));      // region-local tile index
+    int64_t tp0 = tdiv % a.P;
+    if (tp0 < 0) tp0 += a.P;                              // physical tile index
+    const bool has_edge = (rp0 < E) && ((o0 < H) || (o0 + PPT - 1 + H >= a.W));
+    const int64_t F = 2 * a.P;
+
+    for (int t = 0; t < a.s; ++t) {
+        const int64_t n = a.n0 + t;
+        // ---- edge points of level n: LDS history for later steps, ring for later launches
+        if (has_edge) {
+            const int64_t slot = n % a.R;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                const int rp = rp0 + j;
+                int64_t oj = o0 + j;
+                int e = 0;
+                while (oj >= a.W) { oj -= a.W; ++e; }
+                const bool lo = oj < H, hi = oj >= a.W - H;
+                if (rp < E && (lo || hi)) {
+                    const int side = lo ? 0 : 1;
+                    const int q = lo ? (int)oj : (int)(oj - (a.W - H));
+                    if (t < a.s - 1)
+                        eh[((t * a.NT + (tl0 + e)) * 2 + side) * H + q] = w[H + j];
+                    if (a.publish && rp >= sh && rp < sh + owned) {
+                        int64_t tp = tp0 + e;
+                        while (tp >= a.P) tp -= a.P;
+                        a.ring[((slot * a.P + tp) * 2 + side) * H + q] = w[H + j];
+                    }
+                }
+            }
+        }
+        // ---- neighbour exchange: first and last H values of every thread
+        double *buf = xch + (t & 1) * kThreads * 2 * H;
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            buf[tid * 2 * H + q] = w[H + q];
+            buf[tid * 2 * H + H + q] = w[PPT + q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            w[q] = (tid > 0) ? buf[(tid - 1) * 2 * H + H + q] : 0.0;
+            w[PPT + H + q] = (tid < kThreads - 1) ? buf[(tid + 1) * 2 * H + q] : 0.0;
+        }
+        // ---- standard stencil on every point
+        double res[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            double nb[2 * H];
+#pragma unroll
+            for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
+            res[j] = update<ORDER, LINEAR>(nb, w[H + j], a);
+        }
+        // ---- points next to a tile edge: stencil again with AT halo values
+        if (has_edge) {
+            const int8_t *krow = a.delays + n * F;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                const int rp = rp0 + j;
+                int64_t oj = o0 + j;
+                int e = 0;
+                while (oj >= a.W) { oj -= a.W; ++e; }
+                const bool valid = rp >= (t + 1) * H && rp < E - (t + 1) * H;   // inside the cone
+                if (valid && (oj < H || oj >= a.W - H)) {
+                    int64_t tp = tp0 + e;
+                    while (tp >= a.P) tp -= a.P;
+                    const int tl = tl0 + e;
+                    double nb[2 * H];
+#pragma unroll
+                    for (int sl = 0; sl < 2 * H; ++sl) {
+                        const int d = (sl < H) ? -(H - sl) : (sl - H + 1);
+                        double v = w[H + j + d];
+                        const int64_t od = oj + d;
+                        if (od < 0 || od >= a.W) {
+                            const int side = (od < 0) ? 0 : 1;
+                            const int kk = krow[2 * tp + side];
+                            if (kk > 0) {
+                                const int q = (side == 0) ? (int)(od + H) : (int)(od - a.W);
+                                const int stl = tl + (side ? 1 : -1);
+                                int64_t stp = tp + (side ? 1 : -1);
+                                if (stp < 0) stp += a.P;
+                                if (stp >= a.P) stp -= a.P;
+                                const int sside = 1 - side;
+                                double vv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                                for (int jj = 0; jj < M; ++jj) {
+                                    if (jj == 0 || !a.stale) {
+                                        const int64_t lev = n - kk - jj;
+                                        if (lev >= a.n0)
+                                            vv[jj] = eh[(((int)(lev - a.n0) * a.NT + stl) * 2 + sside) * H + q];
+                                        else
+                                            vv[jj] = a.ring[(((lev % a.R) * a.P + stp) * 2 + sside) * H + q];
+                                    }
+                                }
+                                v = extrap(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
+                            }
+                        }
+                        nb[sl] = v;
+                    }
+                    res[j] = update<ORDER, LINEAR>(nb, w[H + j], a);
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) w[H + j] = res[j];
+    }
+
+    // ---- level n0+s of the owned points: registers -> LDS -> coalesced stores
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) stage[tid * PPT + j + tid] = w[H + j];
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < PPT; ++it) {
+        const int r = it * kThreads + tid;
+        if (r >= sh && r < sh + owned) a.uout[c0 + (r - sh)] = stage[r + r / PPT];
+    }
+}
+
+// Delay array: SplitMix64 (Steele, Lea & Flood 2014) output for the state
+// seed + gamma*(1 + n*F + f), mapped to the distribution by a multiply-shift
+// of the high 32 bits, then clamped to min(k, L, max(0, n - m + 1)).
+__global__ void k_delays(int8_t *out, int64_t total, int64_t F, int L, int m, int dist,
+                         uint64_t seed)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t z = seed + 0x9E3779B97F4A7C15ULL * (uint64_t)(idx + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        z = z ^ (z >> 31);
+        const uint64_t hi = z >> 32, lo = z & 0xFFFFFFFFULL;
+        int k;
+        if (dist == 0) k = (int)((hi * (uint64_t)(L + 1)) >> 32);
+        else k = (L == 0 || lo < 0x80000000ULL) ? 0 : 1 + (int)((hi * (uint64_t)L) >> 32);
+        const int64_t n = idx / F;
+        int64_t lim = n - m + 1;
+        if (lim < 0) lim = 0;
+        if (lim > L) lim = L;
+        out[idx] = (int8_t)(k < lim ? k : lim);
+    }
+}
+
+__global__ void k_fill(double *p, int64_t n, double v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_copy(double *__restrict__ dst, const double *__restrict__ src, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Reductions: per-thread compensated accumulation, wave64 shuffles, one
+// partial per workgroup, then a single-workgroup pass in fixed order.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+// part[b*5 + {0..4}] = max|u|, sum u (s, c), sum|u| (s, c)
+__global__ __launch_bounds__(kThreads) void k_stats_part(const double *u, int64_t n, double *part)
+{
+    double mx = 0.0;
+    Acc s{0.0, 0.0}, sa{0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const double v = u[i];
+        mx = fmax(mx, fabs(v));
+        acc_add(s, v);
+        acc_add(sa, fabs(v));
+    }
+    mx = wave_max(mx);
+    s = wave_acc(s);
+    sa = wave_acc(sa);
+    __shared__ double red[kThreads / 64][5];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[wv][0] = mx; red[wv][1] = s.s; red[wv][2] = s.c; red[wv][3] = sa.s; red[wv][4] = sa.c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0][0];
+        Acc S{red[0][1], red[0][2]}, SA{red[0][3], red[0][4]};
+        for (int q = 1; q < kThreads / 64; ++q) {
+            m = fmax(m, red[q][0]);
+            acc_merge(S, Acc{red[q][1], red[q][2]});
+            acc_merge(SA, Acc{red[q][3], red[q][4]});
+        }
+        double *o = part + (int64_t)blockIdx.x * 5;
+        o[0] = m; o[1] = S.s; o[2] = S.c; o[3] = SA.s; o[4] = SA.c;
+    }
+}
+
+__global__ void k_stats_final(const double *part, int nb, int64_t n, double *out3)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double m = 0.0;
+    Acc S{0.0, 0.0}, SA{0.0, 0.0};
+    for (int b = 0; b < nb; ++b) {
+        const double *o = part + (int64_t)b * 5;
+        m = fmax(m, o[0]);
+        acc_merge(S, Acc{o[1], o[2]});
+        acc_merge(SA, Acc{o[3], o[4]});
+    }
+    out3[0] = m;
+    out3[1] = (S.s + S.c) / (double)n;
+    out3[2] = SA.s + SA.c;
+}
+
+// part[b*2 + {0,1}] = sum 0.5 d^2 (s, c); lam = d = u - t
+__global__ __launch_bounds__(kThreads) void k_loss_part(const double *u, const double *t,
+                                                       double *lam, int64_t n, double *part)
+{
+    Acc s{0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const double d = u[i] - t[i];
+        if (lam) lam[i] = d;
+        acc_add(s, 0.5 * (d * d));
+    }
+    s = wave_acc(s);
+    __shared__ double red[kThreads / 64][2];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) { red[wv][0] = s.s; red[wv][1] = s.c; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Acc S{red[0][0], red[0][1]};
+        for (int q = 1; q < kThreads / 64; ++q) acc_merge(S, Acc{red[q][0], red[q][1]});
+        part[(int64_t)blockIdx.x * 2] = S.s;
+        part[(int64_t)blockIdx.x * 2 + 1] = S.c;
+    }
+}
+
+// out = sum of compensated pairs part[i*2], part[i*2+1], i in order
+__global__ void k_pairs_final(const double *part, int64_t np, double *out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    Acc S{0.0, 0.0};
+    for (int64_t b = 0; b < np; ++b) acc_merge(S, Acc{part[b * 2], part[b * 2 + 1]});
+    out[0] = S.s + S.c;
+}
+
+int grid_for(int64_t n)
+{
+    int64_t g = (n + kThreads - 1) / kThreads;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+int step1d_points_per_thread() { return kPPT; }
+
+size_t step1d_lds_bytes(int order, int s, int NT)
+{
+    const int H = order / 2;
+    const size_t stage = (size_t)kThreads * kPPT + kThreads;
+    const size_t steps = (size_t)2 * kThreads * 2 * H + (size_t)(s > 1 ? s - 1 : 0) * NT * 2 * H;
+    return 8 * (stage > steps ? stage : steps);
+}
+
+hipError_t launch_step1d(const Step1D &a, int order, bool linear, int64_t nblocks,
+                         hipStream_t st)
+{
+    const size_t lds = step1d_lds_bytes(order, a.s, a.NT);
+    dim3 grid((unsigned)nblocks), block(kThreads);
+    if (order == 2) {
+        if (linear) hipLaunchKernelGGL((k_step1d<2, true>), grid, block, lds, st, a);
+        else hipLaunchKernelGGL((k_step1d<2, false>), grid, block, lds, st, a);
+    } else {
+        if (linear) hipLaunchKernelGGL((k_step1d<4, true>), grid, block, lds, st, a);
+        else hipLaunchKernelGGL((k_step1d<4, false>), grid, block, lds, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_delays(int8_t *out, int64_t nsteps, int64_t F, int L, int m, int dist,
+                         uint64_t seed, hipStream_t st)
+{
+    const int64_t total = nsteps * F;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_delays, dim3(grid_for(total)), dim3(kThreads), 0, st, out, total, F, L,
+                       m, dist, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kThreads), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(kThreads), 0, st, dst, src, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const double *u, int64_t n, double *part, double *out3, hipStream_t st)
+{
+    int nb = grid_for(n);
+    if (nb > kRedBlocks) nb = kRedBlocks;
+    hipLaunchKernelGGL(k_stats_part, dim3(nb), dim3(kThreads), 0, st, u, n, part);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, st, part, nb, n, out3);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss(const double *u, const double *t, double *lam, int64_t n, double *part,
+                       double *J, hipStream_t st)
+{
+    int nb = grid_for(n);
+    if (nb > kRedBlocks) nb = kRedBlocks;
+    hipLaunchKernelGGL(k_loss_part, dim3(nb), dim3(kThreads), 0, st, u, t, lam, n, part);
+    hipLaunchKernelGGL(k_pairs_final, dim3(1), dim3(64), 0, st, part, (int64_t)nb, J);
+    return hipGetLastError();
+}
+
+hipError_t launch_gnu_final(const double *part, int64_t nparts, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pairs_final, dim3(1), dim3(64), 0, st, part, nparts, out);
+    return hipGetLastError();
+}
+
+}  // namespace atk

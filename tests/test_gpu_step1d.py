@@ -1,0 +1,320 @@
+"""GPU parity of the 1D AT stepper against the CPU oracle (through the C ABI).
+
+Bar: normwise relative error max|u_gpu - u_oracle| / max|u_oracle| <= 1e-12
+(binary64; both sides evaluate the same operations in the same order without
+contraction, so bit equality is expected and reported); delay arrays
+bit-identical; fused launches bit-identical to one launch per step."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1911_05769_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def stepper(gpu, N, P, order, L, nu, dt, nsteps, dist=0, seed=7, **kw):
+    return gpu.Stepper(n=N, p=P, order=order, L=L, nu=nu, dt=dt, nsteps_max=nsteps, seed=seed,
+                       dist=dist, **kw)
+
+
+def gpu_run(gpu, u0, N, P, order, L, nu, dt, nsteps, fuse=1, **kw):
+    st = stepper(gpu, N, P, order, L, nu, dt, nsteps, **kw)
+    st.set_fuse(fuse)
+    u, s = dev(u0), torch.empty(N, dtype=torch.float64, device="cuda")
+    st.run(u, s, nsteps)
+    return host(u), st
+
+
+# ---------------------------------------------------------------- delays
+
+@pytest.mark.parametrize("nsteps,F,L,m,dist,seed", [
+    (1000, 16, 2, 2, 0, 20191112), (300, 8192, 4, 3, 1, 5), (50, 6, 0, 2, 0, 1),
+    (64, 2048, 15, 3, 0, 2 ** 63 + 11), (40, 3072, 3, 2, 1, 9)])
+def test_delays_bit_identical(gpu, nsteps, F, L, m, dist, seed):
+    log("delays", nsteps, F, L, m, dist, seed)
+    order = 2 if m == 2 else 4
+    P = F // 2
+    st = gpu.Stepper(n=P * 4, p=P, order=order, L=L, nu=0.01, dt=1e-5, nsteps_max=nsteps,
+                     seed=seed, dist=dist)
+    assert np.array_equal(st.delays(), oracle.delays(nsteps, F, L, m, dist, seed))
+
+
+def test_host_delays_roundtrip(gpu):
+    k = oracle.delays(30, 16, 3, 2, 0, 4)
+    k[10:, 5] = 3                                     # adversarial: one face always late
+    st = gpu.Stepper(n=256, p=8, order=2, L=3, nu=0.01, dt=1e-4, nsteps_max=30, delays=k)
+    assert np.array_equal(st.delays(), k)
+
+
+# ---------------------------------------------------------------- parity, plain form
+
+CASES = [
+    # name, N, P, order, L, dist, nu, nsteps, extra
+    ("sines_n1024_p8_o2_L2", 1024, 8, 2, 2, 0, 0.05, 1000, {}),
+    ("sines_n1024_p8_o2_sync", 1024, 8, 2, 0, 0, 0.05, 1000, {}),
+    ("powerlaw_n6000_p12_o4_L4", 6000, 12, 4, 4, 1, 1e-3, 400, {}),
+    ("powerlaw_n9000_p9_o2_L3", 9000, 9, 2, 3, 0, 2e-3, 300, {}),
+    ("single_tile_n512_o4", 512, 1, 4, 3, 1, 0.01, 200, {}),
+    ("narrow_tiles_n600_p300_o2", 600, 300, 2, 3, 0, 0.02, 150, {}),
+    ("stale_n2048_p16_o2", 2048, 16, 2, 3, 0, 0.02, 300, {"halo_mode": 1}),
+    ("linear_n2048_p8_o4", 2048, 8, 4, 2, 0, 0.02, 300, {"adv_mode": 1, "adv_speed": 0.8}),
+]
+
+
+def _inputs(N, nu, seed=3):
+    u0 = I.u0_sines(N, seed) if N <= 1024 else I.u0_powerlaw(N, max(2, N // 16), seed)
+    dt = I.dt_rule(2 * math.pi / N, float(np.max(np.abs(u0))), nu)
+    return u0, dt
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_parity_plain(gpu, case):
+    name, N, P, order, L, dist, nu, nst, extra = case
+    log("parity", name)
+    u0, dt = _inputs(N, nu)
+    if "adv_speed" in extra:
+        dt = min(dt, 0.2 * (2 * math.pi / N) / extra["adv_speed"])
+    st = stepper(gpu, N, P, order, L, nu, dt, nst, dist=dist, **extra)
+    k = st.delays()
+    if name.endswith("sync"):
+        k = np.zeros_like(k)
+        st = stepper(gpu, N, P, order, L, nu, dt, nst, delays=k, **extra)
+    ref = oracle.run1d(u0, N, P, order, L, nu, dt, k, nst, stale=extra.get("halo_mode") == 1,
+                       linear=extra.get("adv_mode") == 1, adv_speed=extra.get("adv_speed", 0.0))
+    a, b = dev(u0), torch.empty(N, dtype=torch.float64, device="cuda")
+    for n in range(nst):                    # one at_step per step
+        st.step(a, b)
+        a, b = b, a
+    got = host(a)
+    err = relerr(got, ref)
+    log("  rel err %.3e bitwise %s" % (err, np.array_equal(got, ref)))
+    assert err <= TOL
+    assert np.all(np.isfinite(got))
+
+
+# ---------------------------------------------------------------- fused == plain
+
+FUSE_CASES = [
+    ("n4096_p8_o2", 4096, 8, 2, 2, 0, 0.05, 97),
+    ("n6000_p12_o4", 6000, 12, 4, 4, 1, 1e-3, 101),
+    ("tiny_n64_p4_o2", 64, 4, 2, 3, 0, 0.05, 60),
+    ("tiny_n96_p3_o4", 96, 3, 4, 2, 1, 0.02, 70),
+    ("w2_n1000_p500_o2", 1000, 500, 2, 2, 0, 0.02, 40),
+    ("w4_n4000_p1000_o4", 4000, 1000, 4, 2, 1, 0.02, 40),
+    ("ragged_n12345_p5_o4", 12345, 5, 4, 3, 0, 0.01, 77),
+]
+
+
+@pytest.mark.parametrize("case", FUSE_CASES, ids=[c[0] for c in FUSE_CASES])
+def test_fused_equals_plain_and_oracle(gpu, case):
+    name, N, P, order, L, dist, nu, nst = case
+    log("fused", name)
+    u0, dt = _inputs(N, nu)
+    plain, st = gpu_run(gpu, u0, N, P, order, L, nu, dt, nst, fuse=1, dist=dist)
+    ref = oracle.run1d(u0, N, P, order, L, nu, dt, st.delays(), nst)
+    assert relerr(plain, ref) <= TOL
+    for s in (2, 3, 4, 5, 8, 13, 16, 32):
+        try:
+            got, _ = gpu_run(gpu, u0, N, P, order, L, nu, dt, nst, fuse=s, dist=dist)
+        except gpu.AtError as e:
+            assert e.status == gpu.AT_ERR_ARG      # above this grid's limit
+            continue
+        assert np.array_equal(got, plain), "fuse %d differs" % s
+
+
+# ---------------------------------------------------------------- full size (2^24, order 4)
+
+def test_full_size_powerlaw_1d(gpu):
+    """N = 2^24, P = 4096, order 4, L = 4: 200 steps in the autotuned launch
+    configuration against the oracle on the whole grid; then all 2000 steps,
+    fused against one launch per step, bit for bit."""
+    wl = I.wl_powerlaw_1d()
+    N, P = wl.n[0], wl.p[0]
+    log("full size", wl.name)
+    st = stepper(gpu, N, P, wl.order, wl.L, wl.nu, wl.dt, wl.nsteps, dist=wl.dist, seed=wl.seed)
+    u0 = dev(wl.u0)
+    s = st.autotune(u0, 40)
+    log("  autotuned fuse", s)
+    u, scr = u0.clone(), torch.empty_like(u0)
+    st.run(u, scr, 200)
+    k = st.delays()
+    ref = oracle.run1d(wl.u0, N, P, wl.order, wl.L, wl.nu, wl.dt, k, 200)
+    err = relerr(host(u), ref)
+    log("  200 steps rel err %.3e" % err)
+    assert err <= TOL
+    st.run(u, scr, wl.nsteps - 200)
+    st2 = stepper(gpu, N, P, wl.order, wl.L, wl.nu, wl.dt, wl.nsteps, dist=wl.dist, seed=wl.seed)
+    st2.set_fuse(1)
+    v = u0.clone()
+    st2.run(v, scr, wl.nsteps)
+    assert torch.equal(u, v)
+    assert bool(torch.isfinite(u).all())
+
+
+# ---------------------------------------------------------------- state, reductions
+
+def test_snapshot_restore_bitwise(gpu):
+    N, P, nst = 8192, 16, 300
+    u0, dt = _inputs(N, 0.01)
+    full, _ = gpu_run(gpu, u0, N, P, 4, 3, 0.01, dt, nst, fuse=4, dist=1)
+    st = stepper(gpu, N, P, 4, 3, 0.01, dt, nst, dist=1)
+    st.set_fuse(4)
+    u, s = dev(u0), torch.empty(N, dtype=torch.float64, device="cuda")
+    st.run(u, s, 150)
+    snap = st.snapshot(u)
+    st.run(u, s, 50)                   # wander off, then come back
+    u.fill_(0.0)
+    st.restore(snap, u)
+    assert st.n == 150
+    st.run(u, s, 150)
+    assert np.array_equal(host(u), full)
+
+
+def test_autotune_keeps_bits(gpu):
+    N, P, nst = 20000, 40, 120
+    u0, dt = _inputs(N, 0.01)
+    st = stepper(gpu, N, P, 2, 3, 0.01, dt, nst)
+    s = st.autotune(dev(u0), 60)
+    assert st.n == 0 and s >= 1
+    u, scr = dev(u0), torch.empty(N, dtype=torch.float64, device="cuda")
+    st.run(u, scr, nst)
+    plain, _ = gpu_run(gpu, u0, N, P, 2, 3, 0.01, dt, nst, fuse=1)
+    assert np.array_equal(host(u), plain)
+
+
+def test_stats_and_loss(gpu):
+    g = np.random.default_rng(3)
+    for n in (1, 1000, 1 << 20):
+        x = g.standard_normal(n) * 10.0 ** g.uniform(-3, 3, n)
+        y = g.standard_normal(n)
+        st = gpu.Stepper(n=max(n, 2), p=1, order=2, L=0, nu=0.0, dt=1.0, nsteps_max=1) \
+            if n >= 2 else None
+        if st is None:
+            continue
+        out = host(st.stats(dev(x)))
+        mx, mean, sabs = oracle.stats(x)
+        assert out[0] == mx
+        assert abs(out[1] - mean) <= 1e-15 * sabs / n
+        assert abs(out[2] - sabs) <= 1e-15 * sabs
+        lam = torch.empty(n, dtype=torch.float64, device="cuda")
+        J = host(st.loss(dev(x), dev(y), lam))[0]
+        Jr, lr = oracle.loss(x, y)
+        assert abs(J - Jr) <= 1e-14 * Jr
+        assert np.array_equal(host(lam), lr)
+
+
+def test_mean_conserved_sync_on_gpu(gpu):
+    N, P, nst = 1024, 8, 1000
+    u0, dt = _inputs(N, 0.05)
+    st = stepper(gpu, N, P, 2, 0, 0.05, dt, nst)
+    u, s = dev(u0), torch.empty(N, dtype=torch.float64, device="cuda")
+    m0 = host(st.stats(u))[1]
+    st.run(u, s, nst)
+    assert abs(host(st.stats(u))[1] - m0) < 1e-15
+
+
+# ---------------------------------------------------------------- adjoint
+
+ADJ_CASES = [
+    ("o2_n2048_p16_L3", 2048, 16, 2, 3, 0, 0.02, 300, 50, {}),
+    ("o2_n3000_p1_L2", 3000, 1, 2, 2, 0, 0.02, 120, 7, {}),
+    ("o4_n1536_p12_L4", 1536, 12, 4, 4, 1, 0.01, 200, 64, {}),
+    ("o2_stale_n1024_p8", 1024, 8, 2, 3, 0, 0.02, 100, 30, {"halo_mode": 1}),
+    ("o2_linear_n1024_p4", 1024, 4, 2, 2, 0, 0.02, 100, 100, {"adv_mode": 1, "adv_speed": 0.5}),
+]
+
+
+@pytest.mark.parametrize("case", ADJ_CASES, ids=[c[0] for c in ADJ_CASES])
+def test_adjoint_parity(gpu, case):
+    name, N, P, order, L, dist, nu, nst, C, extra = case
+    log("adjoint", name)
+    u0, dt = _inputs(N, nu)
+    tgt = I.u0_powerlaw(N, 16, 99) * 0.5
+    st = stepper(gpu, N, P, order, L, nu, dt, nst, dist=dist, record=True, ckpt_every=C, **extra)
+    u, s = dev(u0), torch.empty(N, dtype=torch.float64, device="cuda")
+    st.run(u, s, nst)
+    lam = torch.empty(N, dtype=torch.float64, device="cuda")
+    st.loss(u, dev(tgt), lam)
+    g, gnu = st.adjoint(lam)
+    k = st.delays()
+    kw = dict(stale=extra.get("halo_mode") == 1, linear=extra.get("adv_mode") == 1,
+              adv_speed=extra.get("adv_speed", 0.0))
+    uT = oracle.run1d(u0, N, P, order, L, nu, dt, k, nst, **kw)
+    J, lamT = oracle.loss(uT, tgt)
+    lam0, gnu_ref = oracle.adjoint1d(u0, lamT, N, P, order, L, nu, dt, k, nst, **kw)
+    e = relerr(host(g), lam0)
+    en = abs(host(gnu)[0] - gnu_ref) / abs(gnu_ref)
+    log("  grad u0 rel %.3e  grad nu rel %.3e" % (e, en))
+    assert e <= TOL
+    assert en <= TOL
+
+
+def test_adjoint_full_size_fd(gpu):
+    """N = 2^20, P = 1024, order 2, L = 3, 4000 steps, checkpoints every 100:
+    directional derivatives of the adjoint gradient against central finite
+    differences (h = 1e-6) on 16 seeded N(0,1) directions, and d/dnu."""
+    wl = I.wl_adjoint_1d()
+    N, P, nst, C = wl.n[0], wl.p[0], wl.nsteps, wl.extra["ckpt"]
+    log("adjoint full size", wl.name)
+    u0 = dev(wl.u0)
+    scr = torch.empty_like(u0)
+
+    def forward(nu, u_init, record=False):
+        st = stepper(gpu, N, P, 2, wl.L, nu, wl.dt, nst, seed=wl.seed, record=record,
+                     ckpt_every=C if record else 0)
+        if not record:
+            st.set_fuse(8)
+        u = u_init.clone()
+        st.run(u, scr, nst)
+        return st, u
+
+    _, target = forward(wl.extra["nu_target"], u0)
+    st, uT = forward(wl.nu, u0, record=True)
+    lam = torch.empty_like(uT)
+    J0 = st.loss(uT, target, lam)
+    g, gnu = st.adjoint(lam)
+    g = host(g)
+    gnu = host(gnu)[0]
+    h = 1e-6
+
+    def J(nu, u_init):
+        stj, u = forward(nu, u_init)
+        return host(stj.loss(u, target))[0]
+
+    dirs = I.fd_directions(N, 16, wl.seed + 1)
+    worst = 0.0
+    for i, d in enumerate(dirs):
+        dd = dev(d)
+        fd = (J(wl.nu, u0 + h * dd) - J(wl.nu, u0 - h * dd)) / (2 * h)
+        ad = float(np.dot(g, d))
+        worst = max(worst, abs(fd - ad) / abs(fd))
+    fdn = (J(wl.nu + h, u0) - J(wl.nu - h, u0)) / (2 * h)
+    en = abs(fdn - gnu) / abs(fdn)
+    log("  worst direction rel %.3e, nu rel %.3e, J %.3e" % (worst, en, host(J0)[0]))
+    assert worst <= 1e-6
+    assert en <= 1e-6
