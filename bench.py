@@ -145,6 +145,24 @@ def cpu_baseline(res):
                        "order 4, same u0 and delays), %.1f s wall" % (steps, el))
 
 
+def calibrate(torch):
+    """Plain device copy of a known size: 2^27 doubles (1 GiB) read and written
+    per launch, 5 launches, for scaling the HBM byte counters."""
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    tm = Timer(torch)
+    for _ in range(5):
+        tm.start()
+        dst.copy_(src)
+        tm.stop()
+    ms = tm.total_ms() / 5
+    eprint("[calibrate] copy of %d bytes: %.3f ms, %.1f GB/s (read+write)" %
+           (8 * n, ms, 16.0 * n / (ms * 1e-3) / 1e9))
+    print(json.dumps({"calibration_bytes_read": 8 * n, "calibration_bytes_written": 8 * n,
+                      "ms_per_copy": ms}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +170,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--only", choices=["main", "all"], default="all")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--fuse", type=int, default=None,
+                    help="steps per launch of the headline run (default: autotuned)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="only copy 1 GiB of doubles 5 times (counter scale reference)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -168,7 +190,10 @@ def main():
         eprint("bench.py: no GPU visible")
         sys.exit(1)
     at.lib()
-    main_res = bench_c2(args, torch, at, I)
+    if args.calibrate:
+        calibrate(torch)
+        return
+    main_res = bench_c2(args, torch, at, I, fuse=args.fuse)
     rl, rl_other = roofline(main_res)
     out = {
         "metric": METRIC,

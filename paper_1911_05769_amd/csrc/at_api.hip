@@ -60,6 +60,14 @@ struct Derived {
     double c1[3], c2[3];
 };
 
+// Region of one workgroup: RL points left of the owned chunk, CH owned, s*h
+// right.  Aligned form (tile width a multiple of the points per thread): RL
+// and CH are multiples of PPT so every thread's points lie in one tile.
+struct Region1D {
+    bool aligned;
+    int64_t RL, CH;
+};
+
 at_status derive(const at_config *c, Derived &d)
 {
     if (!c) return fail(AT_ERR_ARG, "null configuration");
@@ -125,11 +133,15 @@ at_status derive(const at_config *c, Derived &d)
     return AT_OK;
 }
 
-// ring levels: L+m-1 past levels are read while up to kMaxFuse are written;
-// record mode keeps every level of the run (the adjoint re-reads them).
+int max_fuse_1d(const Derived &d);
+
+// ring levels: L+m-1 past levels are read while up to s levels are written
+// (s = the largest steps-per-launch this grid allows); record mode keeps every
+// level of the run (the adjoint re-reads them).
 int ring_levels(const at_config *c, const Derived &d)
 {
-    int64_t R = c->L + d.m - 1 + kMaxFuse;
+    const int smax = d.dim == 1 ? max_fuse_1d(d) : 1;
+    int64_t R = c->L + d.m - 1 + smax;
     if (c->record) R = std::max<int64_t>(R, c->nsteps_max + 1);
     return (int)R;
 }
@@ -190,13 +202,17 @@ at_status make_layout(const at_config *c, const Derived &d, Layout &L)
     return AT_OK;
 }
 
-// Largest steps-per-launch usable for this 1D configuration.
+Region1D region_1d(const Derived &d, int s);
+
+// Largest steps-per-launch usable for this 1D configuration: the owned chunk
+// stays at least half the region (or the whole grid) and the LDS edge
+// history fits in 64 KiB.
 int max_fuse_1d(const Derived &d)
 {
     const int reg = kThreads * step1d_points_per_thread();
     int best = 1;
-    for (int s = 1; s <= kMaxFuse; ++s) {
-        if (reg - 2 * s * d.h < std::min<int64_t>(reg / 2, d.N) && s > 1) break;
+    for (int s = 2; s <= kMaxFuse; ++s) {
+        if (region_1d(d, s).CH < std::min<int64_t>(reg / 2, d.N)) break;
         const int NT = (int)((reg - 1) / d.W + 2);
         if (step1d_lds_bytes(d.order, s, NT) > 64 * 1024) break;
         best = s;
@@ -204,10 +220,28 @@ int max_fuse_1d(const Derived &d)
     return best;
 }
 
+Region1D region_1d(const Derived &d, int s)
+{
+    const int ppt = step1d_points_per_thread();
+    const int64_t reg = (int64_t)kThreads * ppt;
+    Region1D r;
+    r.aligned = d.W % ppt == 0;
+    if (r.aligned) {
+        r.RL = ((int64_t)s * d.h + ppt - 1) / ppt * ppt;
+        r.CH = (reg - r.RL - (int64_t)s * d.h) / ppt * ppt;
+    } else {
+        r.RL = (int64_t)s * d.h;
+        r.CH = reg - 2 * (int64_t)s * d.h;
+    }
+    if (r.CH > d.N) r.CH = d.N;
+    return r;
+}
+
 at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int s, int publish)
 {
     const Derived &d = c->d;
     const int reg = kThreads * step1d_points_per_thread();
+    const Region1D rg = region_1d(d, s);
     Step1D a;
     a.uin = uin;
     a.uout = uout;
@@ -217,21 +251,21 @@ at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int 
     a.P = d.P;
     a.W = d.W;
     a.n0 = n0;
-    a.CH = std::min<int64_t>(reg - 2 * s * d.h, d.N);
+    a.CH = rg.CH;
     if (a.CH < 1) return fail(AT_ERR_ARG, "fuse_steps %d too large for this stencil", s);
     a.s = s;
     a.R = c->lay.R;
     a.NT = (int)((reg - 1) / d.W + 2);
     a.stale = c->cfg.halo_mode;
     a.publish = publish;
-    a.pad0 = 0;
+    a.RL = (int32_t)rg.RL;
     a.nu = c->cfg.nu;
     a.dt = c->cfg.dt;
     a.c1 = d.c1[0];
     a.c2 = d.c2[0];
     a.cadv = c->cfg.adv_speed;
     const int64_t nblocks = (d.N + a.CH - 1) / a.CH;
-    AT_HIP(launch_step1d(a, d.order, c->cfg.adv_mode == 1, nblocks, c->st));
+    AT_HIP(launch_step1d(a, d.order, c->cfg.adv_mode == 1, rg.aligned, nblocks, c->st));
     return AT_OK;
 }
 
@@ -262,6 +296,9 @@ at_status launch_any(at_ctx *c, const double *uin, double *uout, int64_t n0, int
     if (c->d.dim == 1) return launch_1d(c, uin, uout, n0, s, publish);
     return at3_launch(c, uin, uout, n0, s, publish);
 }
+
+// doubles in one field: N (1D) or 3N (3D, three components)
+int64_t field_doubles(const at_ctx *c) { return (c->d.dim == 1 ? 1 : 3) * c->d.N; }
 
 int max_fuse(const at_ctx *c)
 {
@@ -410,7 +447,7 @@ at_status at_run(at_ctx *c, double *u, double *scratch, int64_t nsteps)
         c->n += s;
         left -= s;
     }
-    if (cur != u) AT_HIP(launch_copy(u, cur, c->d.N, c->st));
+    if (cur != u) AT_HIP(launch_copy(u, cur, field_doubles(c), c->st));
     return AT_OK;
 }
 
@@ -435,7 +472,7 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
         float ms_best = 1e30f;
         for (int rep = 0; rep < 2; ++rep) {
             AT_HIP(launch_fill(c->ring, (int64_t)c->lay.R * (int64_t)rlev, 0.0, c->st));
-            AT_HIP(launch_copy(t1, u0, c->d.N, c->st));
+            AT_HIP(launch_copy(t1, u0, field_doubles(c), c->st));
             c->n = 0;
             c->fuse = s;
             AT_HIP(hipEventRecord(e0, c->st));
@@ -471,8 +508,7 @@ at_status at_delays_copy(const at_ctx *c, int8_t *host_out)
 at_status at_snapshot_bytes(const at_ctx *c, uint64_t *bytes)
 {
     if (!c || !bytes) return fail(AT_ERR_ARG, "null argument");
-    const uint64_t comps = c->d.dim == 1 ? 1 : 3;
-    *bytes = align_up(8ull * comps * c->d.N) +
+    *bytes = align_up(8ull * field_doubles(c)) +
              align_up(8ull * c->lay.R * ring_level_doubles(&c->cfg, c->d)) + kAlign;
     return AT_OK;
 }
@@ -480,8 +516,7 @@ at_status at_snapshot_bytes(const at_ctx *c, uint64_t *bytes)
 at_status at_snapshot(at_ctx *c, const double *u, void *dev_buf)
 {
     if (!c || !u || !dev_buf) return fail(AT_ERR_ARG, "null argument");
-    const uint64_t comps = c->d.dim == 1 ? 1 : 3;
-    const uint64_t nu = comps * c->d.N, nr = (uint64_t)c->lay.R * ring_level_doubles(&c->cfg, c->d);
+    const uint64_t nu = field_doubles(c), nr = (uint64_t)c->lay.R * ring_level_doubles(&c->cfg, c->d);
     char *b = (char *)dev_buf;
     AT_HIP(launch_copy((double *)b, u, nu, c->st));
     AT_HIP(launch_copy((double *)(b + align_up(8 * nu)), c->ring, nr, c->st));
@@ -495,8 +530,7 @@ at_status at_snapshot(at_ctx *c, const double *u, void *dev_buf)
 at_status at_restore(at_ctx *c, const void *dev_buf, double *u)
 {
     if (!c || !u || !dev_buf) return fail(AT_ERR_ARG, "null argument");
-    const uint64_t comps = c->d.dim == 1 ? 1 : 3;
-    const uint64_t nu = comps * c->d.N, nr = (uint64_t)c->lay.R * ring_level_doubles(&c->cfg, c->d);
+    const uint64_t nu = field_doubles(c), nr = (uint64_t)c->lay.R * ring_level_doubles(&c->cfg, c->d);
     const char *b = (const char *)dev_buf;
     double nn = 0.0;
     AT_HIP(hipMemcpyAsync(&nn, b + align_up(8 * nu) + align_up(8 * nr), sizeof nn,
@@ -513,7 +547,7 @@ at_status at_restore(at_ctx *c, const void *dev_buf, double *u)
 at_status at_stats(at_ctx *c, const double *u, double *out3)
 {
     if (!c || !u || !out3) return fail(AT_ERR_ARG, "null argument");
-    const int64_t n = (c->d.dim == 1 ? 1 : 3) * c->d.N;
+    const int64_t n = field_doubles(c);
     AT_HIP(launch_stats(u, n, c->red, out3, c->st));
     return AT_OK;
 }
@@ -521,7 +555,7 @@ at_status at_stats(at_ctx *c, const double *u, double *out3)
 at_status at_loss(at_ctx *c, const double *u, const double *target, double *lam, double *J_dev)
 {
     if (!c || !u || !target || !J_dev) return fail(AT_ERR_ARG, "null argument");
-    const int64_t n = (c->d.dim == 1 ? 1 : 3) * c->d.N;
+    const int64_t n = field_doubles(c);
     AT_HIP(launch_loss(u, target, lam, n, c->red, J_dev, c->st));
     return AT_OK;
 }

@@ -25,7 +25,7 @@ struct Step1D {
     int32_t NT;               // region-local tile slots in the LDS edge history
     int32_t stale;            // 1: halo = level n-k without extrapolation
     int32_t publish;          // 1: write level n edges to the ring
-    int32_t pad0;
+    int32_t RL;               // left rim of the loaded region (aligned kernel)
     double nu, dt, c1, c2, cadv;
 };
 
@@ -82,8 +82,8 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
 size_t step1d_lds_bytes(int order, int s, int NT);
 int step1d_points_per_thread();
-hipError_t launch_step1d(const Step1D &a, int order, bool linear, int64_t nblocks,
-                         hipStream_t st);
+hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned,
+                         int64_t nblocks, hipStream_t st);
 hipError_t launch_adj1d(const Adj1D &a, int order, bool linear, int64_t nblocks,
                         hipStream_t st);
 int adj1d_points_per_block();

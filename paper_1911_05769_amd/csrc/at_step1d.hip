@@ -236,6 +236,154 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
     }
 }
 
+
+// Aligned variant: the tile width is a multiple of PPT and the region starts
+// on a multiple of PPT, so every thread's PPT points lie in one tile.  A
+// thread that starts a tile writes its left AT halo values into the left
+// part of its register window, a thread that ends a tile its right ones, and
+// then every point runs the same stencil (the split of section 5.2); the
+// window slots replaced belong to this thread alone.
+template <int ORDER, bool LINEAR>
+__global__ __launch_bounds__(kThreads) void k_step1d_aligned(Step1D a)
+{
+    constexpr int H = ORDER / 2;
+    constexpr int M = (ORDER == 2) ? 2 : 3;
+    constexpr int PPT = kPPT;
+    extern __shared__ double lds[];
+    double *stage = lds;                                  // [kThreads*PPT + kThreads]
+    double *xch = lds;                                    // [2][kThreads][2H]  (aliases stage)
+    double *eh = lds + 2 * kThreads * 2 * H;              // [s-1][NT][2][H]    (aliases stage)
+
+    const int tid = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * a.CH;
+    const int owned = (int)((a.N - c0 < a.CH) ? (a.N - c0) : a.CH);
+    const int sh = a.s * H;
+    const int E = a.RL + owned + sh;                      // region length (<= kThreads*PPT)
+    const int64_t G0 = c0 - a.RL;                         // unwrapped start, multiple of PPT
+    int64_t G0w = G0 % a.N;
+    if (G0w < 0) G0w += a.N;
+
+#pragma unroll
+    for (int it = 0; it < PPT; ++it) {
+        const int r = it * kThreads + tid;
+        double v = 0.0;
+        if (r < E) {
+            int64_t g = G0w + r;
+            while (g >= a.N) g -= a.N;
+            v = a.uin[g];
+        }
+        stage[r + r / PPT] = v;
+    }
+    __syncthreads();
+    double w[PPT + 2 * H];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) w[H + j] = stage[tid * PPT + j + tid];
+#pragma unroll
+    for (int q = 0; q < H; ++q) { w[q] = 0.0; w[PPT + H + q] = 0.0; }
+    __syncthreads();
+
+    const int rp0 = tid * PPT;
+    const int64_t Gt = G0 + rp0;
+    const int64_t tdiv = floordiv(Gt, a.W);
+    const int o0 = (int)(Gt - tdiv * a.W);                // multiple of PPT
+    const int tl0 = (int)(tdiv - floordiv(G0, a.W));
+    int64_t tp0 = tdiv % a.P;
+    if (tp0 < 0) tp0 += a.P;
+    const int64_t tpl = tp0 == 0 ? a.P - 1 : tp0 - 1;     // left / right neighbour tiles
+    const int64_t tpr = tp0 == a.P - 1 ? 0 : tp0 + 1;
+    // tile edges of every thread with points in the region: their values may
+    // still be inside the dependency cone of the owned points even when the
+    // thread sticks out of the region
+    const bool lo_edge = o0 == 0 && rp0 < E;
+    const bool hi_edge = o0 + PPT == a.W && rp0 < E;
+    const bool owns = rp0 >= a.RL && rp0 < a.RL + owned;
+    const int64_t F = 2 * a.P;
+
+    for (int t = 0; t < a.s; ++t) {
+        const int64_t n = a.n0 + t;
+        const int64_t slot = n % a.R;
+        // ---- record this level's tile edges (LDS history; ring when owned)
+        if (lo_edge || hi_edge) {
+#pragma unroll
+            for (int q = 0; q < H; ++q) {
+                if (lo_edge) {
+                    if (t < a.s - 1) eh[((t * a.NT + tl0) * 2 + 0) * H + q] = w[H + q];
+                    if (a.publish && owns) a.ring[((slot * a.P + tp0) * 2 + 0) * H + q] = w[H + q];
+                }
+                if (hi_edge) {
+                    if (t < a.s - 1) eh[((t * a.NT + tl0) * 2 + 1) * H + q] = w[PPT + q];
+                    if (a.publish && owns) a.ring[((slot * a.P + tp0) * 2 + 1) * H + q] = w[PPT + q];
+                }
+            }
+        }
+        // ---- neighbour exchange
+        double *buf = xch + (t & 1) * kThreads * 2 * H;
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            buf[tid * 2 * H + q] = w[H + q];
+            buf[tid * 2 * H + H + q] = w[PPT + q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            w[q] = (tid > 0) ? buf[(tid - 1) * 2 * H + H + q] : 0.0;
+            w[PPT + H + q] = (tid < kThreads - 1) ? buf[(tid + 1) * 2 * H + q] : 0.0;
+        }
+        // ---- AT halo approximation at tile edges (k = 0: the raw neighbour stays)
+        if (lo_edge || hi_edge) {
+            const int8_t *krow = a.delays + n * F;
+            const int kl = (lo_edge && tid > 0) ? krow[2 * tp0 + 0] : 0;   // tid 0: no left source
+            const int kr = hi_edge ? krow[2 * tp0 + 1] : 0;
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const int kk = side == 0 ? kl : kr;
+                if (kk > 0) {
+                    const int stl = side == 0 ? tl0 - 1 : tl0 + 1;
+                    const int64_t stp = side == 0 ? tpl : tpr;
+                    const int sside = 1 - side;
+#pragma unroll
+                    for (int q = 0; q < H; ++q) {
+                        double vv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int jj = 0; jj < M; ++jj) {
+                            if (jj == 0 || !a.stale) {
+                                const int64_t lev = n - kk - jj;
+                                vv[jj] = (lev >= a.n0)
+                                    ? eh[(((int)(lev - a.n0) * a.NT + stl) * 2 + sside) * H + q]
+                                    : a.ring[(((lev % a.R) * a.P + stp) * 2 + sside) * H + q];
+                            }
+                        }
+                        const double hv = extrap(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
+                        if (side == 0) w[q] = hv;
+                        else w[PPT + H + q] = hv;
+                    }
+                }
+            }
+        }
+        // ---- the standard stencil on every point
+        double res[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            double nb[2 * H];
+#pragma unroll
+            for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
+            res[j] = update<ORDER, LINEAR>(nb, w[H + j], a);
+        }
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) w[H + j] = res[j];
+    }
+
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) stage[tid * PPT + j + tid] = w[H + j];
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < PPT; ++it) {
+        const int r = it * kThreads + tid;
+        if (r >= a.RL && r < a.RL + owned) a.uout[c0 + (r - a.RL)] = stage[r + r / PPT];
+    }
+}
+
 // Delay array: SplitMix64 (Steele, Lea & Flood 2014) output for the state
 // seed + gamma*(1 + n*F + f), mapped to the distribution by a multiply-shift
 // of the high 32 bits, then clamped to min(k, L, max(0, n - m + 1)).
@@ -388,11 +536,21 @@ size_t step1d_lds_bytes(int order, int s, int NT)
     return 8 * (stage > steps ? stage : steps);
 }
 
-hipError_t launch_step1d(const Step1D &a, int order, bool linear, int64_t nblocks,
-                         hipStream_t st)
+hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned,
+                         int64_t nblocks, hipStream_t st)
 {
     const size_t lds = step1d_lds_bytes(order, a.s, a.NT);
     dim3 grid((unsigned)nblocks), block(kThreads);
+    if (aligned) {
+        if (order == 2) {
+            if (linear) hipLaunchKernelGGL((k_step1d_aligned<2, true>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_step1d_aligned<2, false>), grid, block, lds, st, a);
+        } else {
+            if (linear) hipLaunchKernelGGL((k_step1d_aligned<4, true>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_step1d_aligned<4, false>), grid, block, lds, st, a);
+        }
+        return hipGetLastError();
+    }
     if (order == 2) {
         if (linear) hipLaunchKernelGGL((k_step1d<2, true>), grid, block, lds, st, a);
         else hipLaunchKernelGGL((k_step1d<2, false>), grid, block, lds, st, a);

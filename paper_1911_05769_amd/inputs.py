@@ -104,6 +104,26 @@ def u0_solenoidal(n: int, kmax: int, seed: int) -> np.ndarray:
     return np.ascontiguousarray(out)
 
 
+def u0_modes3d(n, nmodes: int, kmax: int, seed: int) -> np.ndarray:
+    """Smooth vector field u[3][nz][ny][nx] on a periodic box of any shape:
+    per component a sum of nmodes sines with integer wavevectors in
+    [-kmax, kmax]^3 and random phases, scaled to max |u_i| = 1."""
+    nx, ny, nz = n
+    g = rng(seed)
+    z = np.arange(nz) * (TWO_PI / nz)
+    y = np.arange(ny) * (TWO_PI / ny)
+    x = np.arange(nx) * (TWO_PI / nx)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    out = np.zeros((3, nz, ny, nx))
+    for c in range(3):
+        for _ in range(nmodes):
+            k = g.integers(-kmax, kmax + 1, size=3)
+            out[c] += g.uniform(0.2, 1.0) * np.sin(k[0] * X + k[1] * Y + k[2] * Z +
+                                                   g.uniform(0.0, TWO_PI))
+    out /= max(np.max(np.abs(out)), 1e-300)
+    return np.ascontiguousarray(out)
+
+
 def dt_rule(dx: float, max_abs_u: float, nu: float, cfl: float = 0.2) -> float:
     """dt = cfl * min(dx / max|u|, dx^2 / (2 nu))."""
     adv = dx / max_abs_u if max_abs_u > 0 else math.inf
