@@ -238,8 +238,165 @@ def main():
         out["cpu_baseline"] = cpu_baseline(main_res)
     print(json.dumps(out), flush=True)
 
+def _timed(torch, fn):
+    tm = Timer(torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tm.start()
+    fn()
+    tm.stop()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, tm.total_ms() * 1e-3
 
-EXTRA = []
+
+def bench_batched(args, torch, at, I):
+    """256 independent 1D instances (uneven N, nu, L, seeds), order 4, 500
+    steps: (i) one launch per instance per step, (ii) one launch per step over
+    all instances, (iii) the fused batched form replayed from a HIP graph."""
+    wls = I.batch_instances()
+    nst = wls[0].nsteps
+    pts = sum(w.n[0] for w in wls)
+    u0 = [torch.from_numpy(w.u0).cuda() for w in wls]
+    us = [u.clone() for u in u0]
+    ss = [torch.empty_like(u) for u in u0]
+    res = {"instances": len(wls), "points": pts, "nsteps": nst}
+    # (i) per-instance plain runs
+    steppers = [at.Stepper(n=w.n[0], p=w.p[0], order=w.order, L=w.L, nu=w.nu, dt=w.dt,
+                           nsteps_max=nst, seed=w.seed, dist=w.dist) for w in wls]
+    snaps = [st.snapshot(u) for st, u in zip(steppers, u0)]
+
+    def per_instance():
+        for st, sn, u, s in zip(steppers, snaps, us, ss):
+            st.restore(sn, u)
+            st.run(u, s, nst)
+    per_instance()
+    w1, k1 = _timed(torch, per_instance)
+    ref = [u.clone() for u in us]
+    del steppers, snaps
+    # (ii) batched, one launch per step, no graph; (iii) fused + graph
+    b = at.Batch.from_workloads(wls)
+
+    def batched(use_graph):
+        b.reset()
+        for u, v in zip(us, u0):
+            u.copy_(v)
+        b.run(us, ss, nst, use_graph=use_graph)
+
+    b.set_fuse(1)
+    batched(False)
+    w2, k2 = _timed(torch, lambda: batched(False))
+    b.reset()
+    s = b.autotune(u0, 50)
+    batched(True)                       # capture
+    reps = max(1, args.steps)
+    tm = Timer(torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.reset()
+        for u, v in zip(us, u0):
+            u.copy_(v)
+        tm.start()
+        b.run(us, ss, nst, use_graph=True)
+        tm.stop()
+    torch.cuda.synchronize()
+    w3 = (time.perf_counter() - t0) / reps
+    k3 = tm.total_ms() * 1e-3 / reps
+    same = all(torch.equal(a, r) for a, r in zip(us, ref))
+    upd = pts * nst
+    algo = sum(algo_bytes_1d(w.n[0], w.p[0], w.order, w.L, w.dist, 1) for w in wls) * nst
+    res.update({
+        "value": upd / k3, "unit": "grid-point updates/s", "fuse_steps": s,
+        "ms_graph_run": round(k3 * 1e3, 3),
+        "ms_per_instance_plain": round(k1 * 1e3, 3),
+        "ms_one_launch_per_step": round(k2 * 1e3, 3),
+        "speedup_vs_per_instance": round(k1 / k3, 2),
+        "speedup_vs_one_launch_per_step": round(k2 / k3, 2),
+        "one_launch_per_step_hbm_gbps": round(algo / k2 / 1e9, 1),
+        "bitwise_equal_to_per_instance": bool(same)})
+    eprint("[batched] %d instances, %d points: per-instance %.1f ms, one launch/step %.1f ms, "
+           "fused(s=%d)+graph %.2f ms (%.3g updates/s)" % (len(wls), pts, k1 * 1e3, k2 * 1e3, s,
+                                                           k3 * 1e3, upd / k3))
+    return res
+
+
+def bench_adjoint(args, torch, at, I):
+    """Gradient of 0.5||u(T) - u_target||^2 w.r.t. u0 (2^20 values) and nu for
+    4000 steps, order 2, P = 1024, L = 3, checkpoints every 100 steps."""
+    wl = I.wl_adjoint_1d()
+    N, P, nst, C = wl.n[0], wl.p[0], wl.nsteps, wl.extra["ckpt"]
+    u0 = torch.from_numpy(wl.u0).cuda()
+    scr = torch.empty_like(u0)
+    tst = at.Stepper(n=N, p=P, order=2, L=wl.L, nu=wl.extra["nu_target"], dt=wl.dt,
+                     nsteps_max=nst, seed=wl.seed, fuse_steps=8)
+    target = u0.clone()
+    tst.run(target, scr, nst)
+    times = []
+    for rep in range(max(1, args.steps)):
+        st = at.Stepper(n=N, p=P, order=2, L=wl.L, nu=wl.nu, dt=wl.dt, nsteps_max=nst,
+                        seed=wl.seed, record=True, ckpt_every=C, fuse_steps=8)
+        u = u0.clone()
+        lam = torch.empty_like(u)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        st.run(u, scr, nst)
+        J = st.loss(u, target, lam)
+        ev[1].record()
+        g, gnu = st.adjoint(lam)
+        ev[2].record()
+        torch.cuda.synchronize()
+        times.append((ev[0].elapsed_time(ev[1]) * 1e-3, ev[1].elapsed_time(ev[2]) * 1e-3))
+    tf = min(t[0] for t in times)
+    ta = min(t[1] for t in times)
+    pstep = N * nst
+    # reverse sweep: recompute (16 B) + reverse step (lambda in, u in, lambda out: 24 B)
+    gbps = pstep * 40.0 / ta / 1e9
+    eprint("[adjoint] forward %.2f ms, adjoint %.2f ms (%.0f GB/s algorithmic), J %.3e, "
+           "dJ/dnu %.4e" % (tf * 1e3, ta * 1e3, gbps, float(J), float(gnu)))
+    return {"value": pstep / (tf + ta), "unit": "point-steps/s (gradient)",
+            "ms_forward_recorded": round(tf * 1e3, 3), "ms_adjoint": round(ta * 1e3, 3),
+            "adjoint_hbm_gbps": round(gbps, 1), "adjoint_hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
+            "n": N, "nsteps": nst, "ckpt_every": C}
+
+
+def bench_3d(args, torch, at, I):
+    """3D vector Burgers, 512^3 x 3 components, 8^3 blocks of 64^3, order 2,
+    L = 3, 200 steps."""
+    wl = I.wl_solenoidal_3d()
+    st = at.Stepper(dim=3, n=wl.n, p=wl.p, order=2, L=wl.L, nu=wl.nu, dt=wl.dt,
+                    nsteps_max=wl.nsteps, seed=wl.seed, dist=wl.dist)
+    u0 = torch.from_numpy(wl.u0).cuda()
+    snap = st.snapshot(u0)
+    u = torch.empty_like(u0)
+    s = torch.empty_like(u0)
+    st.restore(snap, u)
+    st.run(u, s, wl.nsteps)
+    reps = max(1, min(args.steps, 3))
+    tm = Timer(torch)
+    for _ in range(reps):
+        st.restore(snap, u)
+        tm.start()
+        st.run(u, s, wl.nsteps)
+        tm.stop()
+    sec = tm.total_ms() * 1e-3 / reps
+    npt = wl.npoints
+    # per point-update: 3 components in and out (48 B); ring: publish 6 faces,
+    # read m = 2 levels of the faces with k > 0 (L/(L+1) of them); delays
+    bx = wl.n[0] // wl.p[0]
+    face_frac = 6.0 / bx
+    ring_b = face_frac * 24 * (1 + 2 * wl.L / (wl.L + 1.0))
+    bpu = 48.0 + ring_b
+    gbps = npt * wl.nsteps * bpu / sec / 1e9
+    eprint("[3d] %s: %.2f ms/run, %.3g point-updates/s, %.0f GB/s (%.1f B/update)" %
+           (wl.name, sec * 1e3, npt * wl.nsteps / sec, gbps, bpu))
+    return {"value": npt * wl.nsteps / sec, "unit": "point-updates/s (3 components)",
+            "ms_per_run": round(sec * 1e3, 3), "hbm_gbps": round(gbps, 1),
+            "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4), "bytes_per_update": round(bpu, 2),
+            "workload": wl.name, "kernel_us_per_step": round(sec * 1e6 / wl.nsteps, 2)}
+
+
+EXTRA = [("batched", bench_batched), ("adjoint", bench_adjoint), ("3d", bench_3d)]
 
 if __name__ == "__main__":
     main()

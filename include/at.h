@@ -178,9 +178,12 @@ at_status at_adjoint(at_ctx *ctx, const double *lambda_T, double *grad_u0, doubl
 typedef struct at_batch at_batch;
 
 /* cfgs[0..count-1] are 1D configurations (record = 0) that all share one
- * order and one stream (the first one's).  Each instance's workspace fields
- * are ignored; the batch uses the single workspace given here, of at least
- * at_batch_workspace_bytes() bytes. */
+ * order, one adv_mode and one stream (the first one's), with tile widths that
+ * are multiples of 16 (AT_ERR_SHAPE otherwise).  Each instance keeps its own
+ * n, p, nu, dt, L, delays (generated or host) and ring.  Instance workspace
+ * fields are ignored; the batch uses the single workspace given here, of at
+ * least at_batch_workspace_bytes() bytes.  All instances share the step
+ * counter, which starts at 0; a run may not pass the smallest nsteps_max. */
 at_status at_batch_workspace_bytes(const at_config *cfgs, int32_t count, uint64_t *bytes);
 at_status at_batch_init(const at_config *cfgs, int32_t count, void *workspace,
                         uint64_t workspace_bytes, at_batch **out);
@@ -192,12 +195,23 @@ void at_batch_free(at_batch *b);
 at_status at_batch_run(at_batch *b, double *const *u_dev, double *const *scratch_dev,
                        int64_t nsteps, int32_t use_graph);
 
+/* Clear every instance's ring and set the shared step counter to 0
+ * (asynchronous; the caller reloads the fields). */
+at_status at_batch_reset(at_batch *b);
+
+/* Shared step counter, steps per launch in use and its upper limit. */
+at_status at_batch_query(const at_batch *b, int64_t *n, int32_t *fuse_steps, int32_t *max_fuse);
+
 /* Choose the batch's steps per launch by timing (same contract as
  * at_autotune, per batch). */
 at_status at_batch_autotune(at_batch *b, double *const *u_dev, double *const *t1,
                             double *const *t2, int32_t trial_steps, int32_t *chosen);
 at_status at_batch_set_fuse(at_batch *b, int32_t fuse_steps);
 at_status at_set_fuse(at_ctx *ctx, int32_t fuse_steps);
+
+/* Size of at_config as compiled into the library (bindings check their
+ * copy of the layout against it). */
+uint64_t at_config_bytes(void);
 
 /* Thread-local message of the last failure in this thread ("" if none). */
 const char *at_last_error(void);

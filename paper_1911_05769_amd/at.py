@@ -91,6 +91,8 @@ SIGNATURES = {
     "at_batch_run": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_int32]),
     "at_batch_autotune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P]),
     "at_batch_set_fuse": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "at_batch_reset": (ctypes.c_int, [_P]),
+    "at_batch_query": (ctypes.c_int, [_P, _P, _P, _P]),
 }
 
 
@@ -333,6 +335,13 @@ class Batch:
                "at_batch_init")
         self._keep = []
 
+    @classmethod
+    def from_workloads(cls, wls, device="cuda", fuse_steps=1):
+        """Instances from inputs.Workload objects (1D)."""
+        ins = [dict(n=w.n[0], p=w.p[0], order=w.order, L=w.L, nu=w.nu, dt=w.dt,
+                    nsteps_max=w.nsteps, seed=w.seed, dist=w.dist, length=w.length) for w in wls]
+        return cls(ins, device=device, fuse_steps=fuse_steps)
+
     def __del__(self):
         try:
             if self._h:
@@ -365,3 +374,12 @@ class Batch:
 
     def set_fuse(self, s: int):
         _check(lib().at_batch_set_fuse(self._h, int(s)), "at_batch_set_fuse")
+
+    def reset(self):
+        _check(lib().at_batch_reset(self._h), "at_batch_reset")
+
+    def query(self):
+        n, s, m = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().at_batch_query(self._h, ctypes.byref(n), ctypes.byref(s), ctypes.byref(m)),
+               "at_batch_query")
+        return int(n.value), int(s.value), int(m.value)

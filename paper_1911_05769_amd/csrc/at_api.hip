@@ -612,3 +612,403 @@ at_status at_adjoint(at_ctx *c, const double *lambda_T, double *grad_u0, double 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form: independent 1D instances advanced by shared launches
+// ---------------------------------------------------------------------------
+
+struct at_batch {
+    int count = 0, order = 2;
+    bool linear = false;
+    hipStream_t st = nullptr;
+    std::vector<at_config> cfg;
+    std::vector<Derived> d;
+    std::vector<int> R;
+    std::vector<int8_t *> delays;
+    std::vector<double *> ring;
+    std::vector<int64_t> ring_doubles;
+    int64_t nsteps_max = 0;   // smallest over the instances
+    int max_fuse = 1, fuse = 1;
+    int64_t n = 0;
+    // device tables (two slots: the run's s and its tail)
+    Step1D *desc_dev[2] = {nullptr, nullptr};
+    int2 *tbl_dev[2] = {nullptr, nullptr};
+    int64_t tbl_cap = 0;
+    int slot_s[2] = {0, 0};
+    int64_t slot_blocks[2] = {0, 0};
+    size_t slot_lds[2] = {0, 0};
+    uint64_t slot_key[2] = {0, 0};
+    std::vector<Step1D> hdesc[2];
+    std::vector<int2> htbl[2];
+    // cached graph of one whole run, captured on a private stream (the
+    // caller's stream may be the null stream, which cannot be captured)
+    hipStream_t cap = nullptr;
+    bool has_graph = false;
+    hipGraphExec_t gexec = nullptr;
+    int64_t g_n0 = -1, g_nsteps = -1;
+    int g_fuse = 0;
+    uint64_t g_key = 0;
+};
+
+namespace {
+
+uint64_t ptr_key(double *const *u, double *const *s, int count)
+{
+    uint64_t h = 1469598103934665603ULL;
+    for (int j = 0; j < count; ++j) {
+        h = (h ^ (uint64_t)(uintptr_t)u[j]) * 1099511628211ULL;
+        h = (h ^ (uint64_t)(uintptr_t)s[j]) * 1099511628211ULL;
+    }
+    return h;
+}
+
+void drop_graph(at_batch *b)
+{
+    if (b->has_graph) (void)hipGraphExecDestroy(b->gexec);
+    b->has_graph = false;
+    b->gexec = nullptr;
+}
+
+at_status batch_tables(at_batch *b, int slot, int s, double *const *u, double *const *scr,
+                       uint64_t key)
+{
+    const uint64_t k2 = key ^ ((uint64_t)s * 0x9E3779B97F4A7C15ULL);
+    if (b->slot_s[slot] == s && b->slot_key[slot] == k2) return AT_OK;
+    drop_graph(b);    // a cached graph reads these tables
+    const int reg = kThreads * step1d_points_per_thread();
+    std::vector<Step1D> &D = b->hdesc[slot];
+    std::vector<int2> &T = b->htbl[slot];
+    D.resize(b->count);
+    T.clear();
+    size_t lds = 0;
+    for (int j = 0; j < b->count; ++j) {
+        const Derived &d = b->d[j];
+        const Region1D rg = region_1d(d, s);
+        Step1D &a = D[j];
+        a.uin = u[j];
+        a.uout = scr[j];
+        a.ring = b->ring[j];
+        a.delays = b->delays[j];
+        a.N = d.N;
+        a.P = d.P;
+        a.W = d.W;
+        a.n0 = 0;
+        a.CH = rg.CH;
+        a.s = s;
+        a.R = b->R[j];
+        a.NT = (int)((reg - 1) / d.W + 2);
+        a.stale = b->cfg[j].halo_mode;
+        a.publish = 1;
+        a.RL = (int32_t)rg.RL;
+        a.nu = b->cfg[j].nu;
+        a.dt = b->cfg[j].dt;
+        a.c1 = d.c1[0];
+        a.c2 = d.c2[0];
+        a.cadv = b->cfg[j].adv_speed;
+        const int64_t nch = (d.N + rg.CH - 1) / rg.CH;
+        for (int64_t c = 0; c < nch; ++c) T.push_back(make_int2(j, (int)c));
+        lds = std::max(lds, step1d_lds_bytes(b->order, s, a.NT));
+    }
+    if ((int64_t)T.size() > b->tbl_cap) return fail(AT_ERR_STATE, "batch block table overflow");
+    AT_HIP(hipStreamSynchronize(b->st));
+    AT_HIP(hipMemcpyAsync(b->desc_dev[slot], D.data(), D.size() * sizeof(Step1D),
+                          hipMemcpyHostToDevice, b->st));
+    AT_HIP(hipMemcpyAsync(b->tbl_dev[slot], T.data(), T.size() * sizeof(int2),
+                          hipMemcpyHostToDevice, b->st));
+    AT_HIP(hipStreamSynchronize(b->st));
+    b->slot_s[slot] = s;
+    b->slot_key[slot] = k2;
+    b->slot_blocks[slot] = (int64_t)T.size();
+    b->slot_lds[slot] = lds;
+    return AT_OK;
+}
+
+// the launches of one run (recorded into a graph when capturing)
+at_status batch_launches(at_batch *b, int64_t n0, int64_t nsteps, double *const *u,
+                         double *const *scr, hipStream_t stream)
+{
+    int flip = 0;
+    int64_t done = 0;
+    while (done < nsteps) {
+        const int s = (int)std::min<int64_t>(b->fuse, nsteps - done);
+        const int slot = s == b->slot_s[0] ? 0 : 1;
+        AT_HIP(launch_step1d_batch(b->desc_dev[slot], b->tbl_dev[slot], b->slot_blocks[slot],
+                                   b->order, b->linear, n0 + done, flip, b->slot_lds[slot], stream));
+        flip ^= 1;
+        done += s;
+    }
+    if (flip)
+        for (int j = 0; j < b->count; ++j)
+            AT_HIP(launch_copy(u[j], scr[j], b->d[j].N, stream));
+    return AT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+static at_status batch_layout(const at_config *cfgs, int32_t count, std::vector<Derived> &ds,
+                              std::vector<uint64_t> &off_delays, std::vector<uint64_t> &off_ring,
+                              std::vector<int> &Rs, uint64_t &off_desc, uint64_t &off_tbl,
+                              int64_t &tbl_cap, int &smax, uint64_t &total)
+{
+    if (!cfgs || count < 1) return fail(AT_ERR_ARG, "batch needs at least one configuration");
+    ds.resize(count);
+    off_delays.resize(count);
+    off_ring.resize(count);
+    Rs.resize(count);
+    smax = kMaxFuse;
+    for (int j = 0; j < count; ++j) {
+        at_status st = derive(&cfgs[j], ds[j]);
+        if (st) return fail(st, "instance %d: %s", j, g_err.c_str());
+        if (cfgs[j].dim != 1) return fail(AT_ERR_ARG, "instance %d: batched form is 1D", j);
+        if (cfgs[j].record) return fail(AT_ERR_ARG, "instance %d: record mode not batched", j);
+        if (cfgs[j].order != cfgs[0].order || cfgs[j].adv_mode != cfgs[0].adv_mode)
+            return fail(AT_ERR_ARG, "instance %d: all instances share order and adv_mode", j);
+        if (ds[j].W % step1d_points_per_thread() != 0)
+            return fail(AT_ERR_SHAPE, "instance %d: tile width %lld is not a multiple of %d", j,
+                        (long long)ds[j].W, step1d_points_per_thread());
+        smax = std::min(smax, max_fuse_1d(ds[j]));
+    }
+    uint64_t off = 0;
+    tbl_cap = 0;
+    for (int j = 0; j < count; ++j) {
+        Rs[j] = cfgs[j].L + ds[j].m - 1 + smax;
+        off_delays[j] = off;
+        off = align_up(off + (uint64_t)cfgs[j].nsteps_max * (uint64_t)ds[j].F);
+        off_ring[j] = off;
+        off = align_up(off + 8ull * (uint64_t)Rs[j] * (uint64_t)ds[j].P * 2 * ds[j].h);
+        int64_t chmin = ds[j].N;
+        for (int s = 1; s <= smax; ++s) chmin = std::min<int64_t>(chmin, region_1d(ds[j], s).CH);
+        tbl_cap += (ds[j].N + chmin - 1) / chmin;
+    }
+    off_desc = off;
+    off = align_up(off + 2ull * count * sizeof(Step1D));
+    off_tbl = off;
+    off = align_up(off + 2ull * (uint64_t)tbl_cap * sizeof(int2));
+    total = off;
+    return AT_OK;
+}
+
+at_status at_batch_workspace_bytes(const at_config *cfgs, int32_t count, uint64_t *bytes)
+{
+    if (!bytes) return fail(AT_ERR_ARG, "null output");
+    std::vector<Derived> ds;
+    std::vector<uint64_t> od, orr;
+    std::vector<int> Rs;
+    uint64_t odesc, otbl, total;
+    int64_t cap;
+    int smax;
+    at_status st = batch_layout(cfgs, count, ds, od, orr, Rs, odesc, otbl, cap, smax, total);
+    if (st) return st;
+    *bytes = total;
+    return AT_OK;
+}
+
+at_status at_batch_init(const at_config *cfgs, int32_t count, void *workspace,
+                        uint64_t workspace_bytes, at_batch **out)
+{
+    if (!out) return fail(AT_ERR_ARG, "null output");
+    *out = nullptr;
+    std::vector<Derived> ds;
+    std::vector<uint64_t> od, orr;
+    std::vector<int> Rs;
+    uint64_t odesc, otbl, total;
+    int64_t cap;
+    int smax;
+    at_status st = batch_layout(cfgs, count, ds, od, orr, Rs, odesc, otbl, cap, smax, total);
+    if (st) return st;
+    if (!workspace || ((uintptr_t)workspace) % kAlign)
+        return fail(AT_ERR_ARG, "workspace NULL or not 256-byte aligned");
+    if (workspace_bytes < total)
+        return fail(AT_ERR_NOMEM, "workspace %llu bytes, need %llu",
+                    (unsigned long long)workspace_bytes, (unsigned long long)total);
+    for (int j = 0; j < count; ++j) {
+        const at_config *c = &cfgs[j];
+        if (c->delay_mode != AT_DELAY_HOST) continue;
+        for (int64_t n = 0; n < c->nsteps_max; ++n) {
+            const int64_t lim = std::min<int64_t>(c->L, std::max<int64_t>(0, n - ds[j].m + 1));
+            for (int64_t f = 0; f < ds[j].F; ++f) {
+                const int k = c->delays_host[n * ds[j].F + f];
+                if (k < 0 || k > lim)
+                    return fail(AT_ERR_DELAY, "instance %d: delay k[%lld][%lld] = %d outside 0..%lld",
+                                j, (long long)n, (long long)f, k, (long long)lim);
+            }
+        }
+    }
+    at_batch *b = new (std::nothrow) at_batch;
+    if (!b) return fail(AT_ERR_NOMEM, "host allocation failed");
+    char *base = (char *)workspace;
+    b->count = count;
+    b->order = cfgs[0].order;
+    b->linear = cfgs[0].adv_mode == 1;
+    b->st = (hipStream_t)cfgs[0].stream;
+    b->cfg.assign(cfgs, cfgs + count);
+    b->d = ds;
+    b->R = Rs;
+    b->max_fuse = smax;
+    b->fuse = cfgs[0].fuse_steps > 0 ? std::min<int>(cfgs[0].fuse_steps, smax) : 1;
+    b->nsteps_max = cfgs[0].nsteps_max;
+    b->tbl_cap = cap;
+    for (int s = 0; s < 2; ++s) {
+        b->desc_dev[s] = (Step1D *)(base + odesc + (uint64_t)s * count * sizeof(Step1D));
+        b->tbl_dev[s] = (int2 *)(base + otbl + (uint64_t)s * cap * sizeof(int2));
+    }
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < count && e == hipSuccess; ++j) {
+        const at_config *c = &cfgs[j];
+        b->cfg[j].delays_host = nullptr;
+        b->nsteps_max = std::min<int64_t>(b->nsteps_max, c->nsteps_max);
+        b->delays.push_back((int8_t *)(base + od[j]));
+        b->ring.push_back((double *)(base + orr[j]));
+        b->ring_doubles.push_back((int64_t)Rs[j] * ds[j].P * 2 * ds[j].h);
+        if (c->delay_mode == AT_DELAY_GENERATE)
+            e = launch_delays(b->delays[j], c->nsteps_max, ds[j].F, c->L, ds[j].m, c->delay_dist,
+                              c->delay_seed, b->st);
+        else if (c->nsteps_max > 0)
+            e = hipMemcpyAsync(b->delays[j], c->delays_host, (size_t)(c->nsteps_max * ds[j].F),
+                               hipMemcpyHostToDevice, b->st);
+        if (e == hipSuccess) e = launch_fill(b->ring[j], b->ring_doubles[j], 0.0, b->st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(AT_ERR_HIP, "at_batch_init: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return AT_OK;
+}
+
+void at_batch_free(at_batch *b)
+{
+    if (!b) return;
+    drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+at_status at_batch_set_fuse(at_batch *b, int32_t s)
+{
+    if (!b) return fail(AT_ERR_ARG, "null batch");
+    if (s < 1 || s > b->max_fuse)
+        return fail(AT_ERR_ARG, "fuse_steps must be in 1..%d for this batch", b->max_fuse);
+    b->fuse = s;
+    return AT_OK;
+}
+
+at_status at_batch_reset(at_batch *b)
+{
+    if (!b) return fail(AT_ERR_ARG, "null batch");
+    for (int j = 0; j < b->count; ++j)
+        AT_HIP(launch_fill(b->ring[j], b->ring_doubles[j], 0.0, b->st));
+    b->n = 0;
+    return AT_OK;
+}
+
+at_status at_batch_run(at_batch *b, double *const *u, double *const *scr, int64_t nsteps,
+                       int32_t use_graph)
+{
+    if (!b || !u || !scr) return fail(AT_ERR_ARG, "null argument");
+    if (nsteps < 0) return fail(AT_ERR_ARG, "nsteps < 0");
+    if (b->n + nsteps > b->nsteps_max)
+        return fail(AT_ERR_STATE, "batch run to step %lld beyond nsteps_max %lld",
+                    (long long)(b->n + nsteps), (long long)b->nsteps_max);
+    for (int j = 0; j < b->count; ++j)
+        if (!u[j] || !scr[j] || u[j] == scr[j]) return fail(AT_ERR_ARG, "instance %d: bad fields", j);
+    if (nsteps == 0) return AT_OK;
+    const uint64_t key = ptr_key(u, scr, b->count);
+    if (use_graph && b->has_graph && b->g_n0 == b->n && b->g_nsteps == nsteps &&
+        b->g_fuse == b->fuse && b->g_key == key) {
+        AT_HIP(hipGraphLaunch(b->gexec, b->st));
+        b->n += nsteps;
+        return AT_OK;
+    }
+    at_status st = batch_tables(b, 0, b->fuse, u, scr, key);
+    if (st) return st;
+    const int tail = (int)(nsteps % b->fuse);
+    if (tail && nsteps > b->fuse) {
+        st = batch_tables(b, 1, tail, u, scr, key);
+        if (st) return st;
+    } else if (tail) {
+        st = batch_tables(b, 0, tail, u, scr, key);    // a single short launch
+        if (st) return st;
+    }
+    if (!use_graph) {
+        st = batch_launches(b, b->n, nsteps, u, scr, b->st);
+        if (st) return st;
+        b->n += nsteps;
+        return AT_OK;
+    }
+    drop_graph(b);
+    if (!b->cap) AT_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    hipGraph_t g;
+    AT_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    st = batch_launches(b, b->n, nsteps, u, scr, b->cap);
+    hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (st) return st;
+    if (e != hipSuccess) return fail(AT_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(AT_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+    b->has_graph = true;
+    b->g_n0 = b->n;
+    b->g_nsteps = nsteps;
+    b->g_fuse = b->fuse;
+    b->g_key = key;
+    AT_HIP(hipGraphLaunch(b->gexec, b->st));
+    b->n += nsteps;
+    return AT_OK;
+}
+
+at_status at_batch_autotune(at_batch *b, double *const *u0, double *const *t1,
+                            double *const *t2, int32_t trial_steps, int32_t *chosen)
+{
+    if (!b || !u0 || !t1 || !t2) return fail(AT_ERR_ARG, "null argument");
+    if (b->n != 0) return fail(AT_ERR_STATE, "autotune needs a batch at step 0");
+    if (trial_steps < 1 || trial_steps > b->nsteps_max)
+        return fail(AT_ERR_ARG, "trial_steps must be in 1..nsteps_max");
+    static const int cands[] = {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32};
+    hipEvent_t e0, e1;
+    AT_HIP(hipEventCreate(&e0));
+    AT_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int best = 1;
+    for (int s : cands) {
+        if (s > b->max_fuse) break;
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            at_status st = at_batch_reset(b);
+            if (st) return st;
+            for (int j = 0; j < b->count; ++j) AT_HIP(launch_copy(t1[j], u0[j], b->d[j].N, b->st));
+            b->fuse = s;
+            AT_HIP(hipEventRecord(e0, b->st));
+            st = at_batch_run(b, t1, t2, trial_steps, 0);
+            if (st) { b->n = 0; return st; }
+            AT_HIP(hipEventRecord(e1, b->st));
+            AT_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            AT_HIP(hipEventElapsedTime(&ms, e0, e1));
+            ms_best = std::min(ms_best, ms);
+        }
+        if (ms_best < best_ms * 0.98f) { best_ms = ms_best; best = s; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    at_status st = at_batch_reset(b);
+    if (st) return st;
+    AT_HIP(hipStreamSynchronize(b->st));
+    b->fuse = best;
+    if (chosen) *chosen = best;
+    return AT_OK;
+}
+
+at_status at_batch_query(const at_batch *b, int64_t *n, int32_t *fuse, int32_t *max_fuse)
+{
+    if (!b) return fail(AT_ERR_ARG, "null batch");
+    if (n) *n = b->n;
+    if (fuse) *fuse = b->fuse;
+    if (max_fuse) *max_fuse = b->max_fuse;
+    return AT_OK;
+}
+
+}  // extern "C"

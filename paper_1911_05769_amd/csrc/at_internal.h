@@ -84,6 +84,8 @@ size_t step1d_lds_bytes(int order, int s, int NT);
 int step1d_points_per_thread();
 hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned,
                          int64_t nblocks, hipStream_t st);
+hipError_t launch_step1d_batch(const Step1D *descs, const int2 *tbl, int64_t nblocks, int order,
+                               bool linear, int64_t n0, int flip, size_t lds, hipStream_t st);
 hipError_t launch_adj1d(const Adj1D &a, int order, bool linear, int64_t nblocks,
                         hipStream_t st);
 int adj1d_points_per_block();

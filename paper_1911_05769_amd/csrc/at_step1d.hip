@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
 // then every point runs the same stencil (the split of section 5.2); the
 // window slots replaced belong to this thread alone.
 template <int ORDER, bool LINEAR>
-__global__ __launch_bounds__(kThreads) void k_step1d_aligned(Step1D a)
+__device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chunk)
 {
     constexpr int H = ORDER / 2;
     constexpr int M = (ORDER == 2) ? 2 : 3;
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d_aligned(Step1D a)
     double *eh = lds + 2 * kThreads * 2 * H;              // [s-1][NT][2][H]    (aliases stage)
 
     const int tid = threadIdx.x;
-    const int64_t c0 = (int64_t)blockIdx.x * a.CH;
+    const int64_t c0 = chunk * a.CH;
     const int owned = (int)((a.N - c0 < a.CH) ? (a.N - c0) : a.CH);
     const int sh = a.s * H;
     const int E = a.RL + owned + sh;                      // region length (<= kThreads*PPT)
@@ -382,6 +382,31 @@ __global__ __launch_bounds__(kThreads) void k_step1d_aligned(Step1D a)
         const int r = it * kThreads + tid;
         if (r >= a.RL && r < a.RL + owned) a.uout[c0 + (r - a.RL)] = stage[r + r / PPT];
     }
+}
+
+template <int ORDER, bool LINEAR>
+__global__ __launch_bounds__(kThreads) void k_step1d_aligned(Step1D a)
+{
+    step1d_aligned_body<ORDER, LINEAR>(a, blockIdx.x);
+}
+
+// Batched form: workgroup b advances chunk tbl[b].y of instance tbl[b].x;
+// instance descriptors carry each instance's grid, ring, delays and
+// coefficients; flip = 1 swaps the field pointers (ping-pong launches).
+template <int ORDER, bool LINEAR>
+__global__ __launch_bounds__(kThreads) void k_step1d_aligned_batch(const Step1D *descs,
+                                                                   const int2 *tbl, int64_t n0,
+                                                                   int flip)
+{
+    const int2 e = tbl[blockIdx.x];
+    Step1D a = descs[e.x];
+    a.n0 = n0;
+    if (flip) {
+        const double *t = a.uin;
+        a.uin = a.uout;
+        a.uout = const_cast<double *>(t);
+    }
+    step1d_aligned_body<ORDER, LINEAR>(a, e.y);
 }
 
 // Delay array: SplitMix64 (Steele, Lea & Flood 2014) output for the state
@@ -557,6 +582,20 @@ hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned,
     } else {
         if (linear) hipLaunchKernelGGL((k_step1d<4, true>), grid, block, lds, st, a);
         else hipLaunchKernelGGL((k_step1d<4, false>), grid, block, lds, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step1d_batch(const Step1D *descs, const int2 *tbl, int64_t nblocks, int order,
+                               bool linear, int64_t n0, int flip, size_t lds, hipStream_t st)
+{
+    dim3 grid((unsigned)nblocks), block(kThreads);
+    if (order == 2) {
+        if (linear) hipLaunchKernelGGL((k_step1d_aligned_batch<2, true>), grid, block, lds, st, descs, tbl, n0, flip);
+        else hipLaunchKernelGGL((k_step1d_aligned_batch<2, false>), grid, block, lds, st, descs, tbl, n0, flip);
+    } else {
+        if (linear) hipLaunchKernelGGL((k_step1d_aligned_batch<4, true>), grid, block, lds, st, descs, tbl, n0, flip);
+        else hipLaunchKernelGGL((k_step1d_aligned_batch<4, false>), grid, block, lds, st, descs, tbl, n0, flip);
     }
     return hipGetLastError();
 }
