@@ -169,6 +169,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--only", choices=["main", "all"], default="all")
+    ap.add_argument("--legs", default="plain,batched,adjoint,3d",
+                    help="comma-separated sub-measurements run with --only all")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fuse", type=int, default=None,
                     help="steps per launch of the headline run (default: autotuned)")
@@ -215,7 +217,8 @@ def main():
         "roofline_other": rl_other,
     }
     paths = {}
-    if args.only == "all":
+    legs = set(x.strip() for x in args.legs.split(",") if x.strip())
+    if args.only == "all" and "plain" in legs:
         plain = bench_c2(args, torch, at, I, fuse=1, label="plain")
         prl, _ = roofline(plain)
         paths["plain_1d"] = {"value": plain["value"], "unit": "grid-point updates/s",
@@ -226,7 +229,10 @@ def main():
                              "fused_speedup": round(main_res["value"] / plain["value"], 3),
                              "bitwise_equal_to_fused": bool(torch.equal(plain["uT"],
                                                                         main_res["uT"]))}
+    if args.only == "all":
         for name, fn in EXTRA:
+            if name not in legs:
+                continue
             try:
                 paths[name] = fn(args, torch, at, I)
             except Exception as e:   # reported, never hidden
@@ -367,6 +373,7 @@ def bench_3d(args, torch, at, I):
     st = at.Stepper(dim=3, n=wl.n, p=wl.p, order=2, L=wl.L, nu=wl.nu, dt=wl.dt,
                     nsteps_max=wl.nsteps, seed=wl.seed, dist=wl.dist)
     u0 = torch.from_numpy(wl.u0).cuda()
+    var = st.autotune(u0, 6)
     snap = st.snapshot(u0)
     u = torch.empty_like(u0)
     s = torch.empty_like(u0)
@@ -388,12 +395,14 @@ def bench_3d(args, torch, at, I):
     ring_b = face_frac * 24 * (1 + 2 * wl.L / (wl.L + 1.0))
     bpu = 48.0 + ring_b
     gbps = npt * wl.nsteps * bpu / sec / 1e9
+    eprint("[3d] variant %d" % var)
     eprint("[3d] %s: %.2f ms/run, %.3g point-updates/s, %.0f GB/s (%.1f B/update)" %
            (wl.name, sec * 1e3, npt * wl.nsteps / sec, gbps, bpu))
     return {"value": npt * wl.nsteps / sec, "unit": "point-updates/s (3 components)",
             "ms_per_run": round(sec * 1e3, 3), "hbm_gbps": round(gbps, 1),
             "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4), "bytes_per_update": round(bpu, 2),
-            "workload": wl.name, "kernel_us_per_step": round(sec * 1e6 / wl.nsteps, 2)}
+            "workload": wl.name, "kernel_us_per_step": round(sec * 1e6 / wl.nsteps, 2),
+            "kernel_variant": var}
 
 
 EXTRA = [("batched", bench_batched), ("adjoint", bench_adjoint), ("3d", bench_3d)]

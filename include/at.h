@@ -134,12 +134,19 @@ at_status at_step(at_ctx *ctx, const double *u_in, double *u_out);
  * steps, counted from n = 0. */
 at_status at_run(at_ctx *ctx, double *u, double *scratch, int64_t nsteps);
 
-/* Choose steps-per-launch s (and nothing else that changes results) by timing
- * `trial_steps` steps from u0 for each candidate; requires n == 0 and leaves
- * the context at n = 0 with the ring cleared.  u0 is not modified; t1 and t2
- * are two scratch fields.  Synchronises the stream.  *chosen receives s. */
+/* Choose steps-per-launch s (1D) or the kernel variant (3D) -- nothing that
+ * changes results -- by timing `trial_steps` steps from u0 for each
+ * candidate; requires n == 0 and leaves the context at n = 0 with the ring
+ * cleared.  u0 is not modified; t1 and t2 are two scratch fields.
+ * Synchronises the stream.  *chosen receives s (1D) or the variant (3D). */
 at_status at_autotune(at_ctx *ctx, const double *u0, double *t1, double *t2,
                       int32_t trial_steps, int32_t *chosen);
+
+/* Kernel variant of a 3D context: 0..5 select the tile height, prefetch
+ * depth and register budget of the 3D stepper (results are bit-identical for
+ * every variant; at_autotune picks one for 3D contexts).  1D contexts accept
+ * only 0. */
+at_status at_set_variant(at_ctx *ctx, int32_t variant);
 
 /* Current step n, steps per launch in use, ring levels R. */
 at_status at_query(const at_ctx *ctx, int64_t *n, int32_t *fuse_steps, int32_t *ring_levels);

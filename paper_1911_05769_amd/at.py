@@ -77,6 +77,7 @@ SIGNATURES = {
     "at_run": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64]),
     "at_autotune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P]),
     "at_set_fuse": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "at_set_variant": (ctypes.c_int, [_P, ctypes.c_int32]),
     "at_query": (ctypes.c_int, [_P, _P, _P, _P]),
     "at_delays_copy": (ctypes.c_int, [_P, _P]),
     "at_snapshot_bytes": (ctypes.c_int, [_P, _P]),
@@ -255,6 +256,9 @@ class Stepper:
 
     def set_fuse(self, s: int):
         _check(lib().at_set_fuse(self._ctx, int(s)), "at_set_fuse")
+
+    def set_variant(self, v: int):
+        _check(lib().at_set_variant(self._ctx, int(v)), "at_set_variant")
 
     def query(self):
         n, s, R = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()

@@ -149,7 +149,8 @@ __global__ __launch_bounds__(kThreads) void k_adj1d(Adj1D a)
                     for (int j = 0; j < M; ++j) {
                         if (j == 0 || !stale) {
                             const int64_t lev = a.n - kk - j;
-                            vv[j] = a.ring[(((lev % a.R) * a.P + stp) * 2 + (1 - side)) * H + q];
+                            // record mode keeps every level: slot = level
+                            vv[j] = a.ring[((lev * a.P + stp) * 2 + (1 - side)) * H + q];
                         }
                     }
                     v = extrap(kk, stale, vv[0], vv[1], vv[2], M);
@@ -195,8 +196,10 @@ __global__ __launch_bounds__(kThreads) void k_adj1d(Adj1D a)
                 const int j = dn - kk;
                 const int need = (kk == 0 || stale) ? 1 : M;
                 if (j < 0 || j >= need) continue;
+                int64_t ms = a.mslot0 + dn;
+                if (ms >= a.Rmu) ms -= a.Rmu;
                 const double m = dn == 0 ? mu_now(fs, q, ri)
-                                         : a.mu[(((n2 % a.Rmu) * a.P + tf) * 2 + fs) * H + q];
+                                         : a.mu[((ms * a.P + tf) * 2 + fs) * H + q];
                 acc += hweight(kk, stale, j, M) * m;
             }
         }
@@ -205,10 +208,10 @@ __global__ __launch_bounds__(kThreads) void k_adj1d(Adj1D a)
         // publish mu^n of this tile's faces (owners: first and last point of the tile)
         if (o == 0)
             for (int q = 0; q < H; ++q)
-                a.mu[(((a.n % a.Rmu) * a.P + t) * 2 + 0) * H + q] = mu_now(0, q, r);
+                a.mu[(((int64_t)a.mslot0 * a.P + t) * 2 + 0) * H + q] = mu_now(0, q, r);
         if (o == a.W - 1)
             for (int q = 0; q < H; ++q)
-                a.mu[(((a.n % a.Rmu) * a.P + t) * 2 + 1) * H + q] = mu_now(1, q, r);
+                a.mu[(((int64_t)a.mslot0 * a.P + t) * 2 + 1) * H + q] = mu_now(1, q, r);
     }
     gacc = wave_acc(gacc);
     const int lane = tid & 63, wv = tid >> 6;

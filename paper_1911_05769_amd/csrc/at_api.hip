@@ -157,6 +157,7 @@ struct at_ctx {
     double *ring, *red, *ckpt, *seg, *lam, *mu, *gnu;
     int64_t n;
     int fuse;
+    int variant;     // 3D kernel variant (tile rows, prefetch depth, register budget)
 };
 
 namespace {
@@ -259,6 +260,8 @@ at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int 
     a.stale = c->cfg.halo_mode;
     a.publish = publish;
     a.RL = (int32_t)rg.RL;
+    a.slot0 = (int32_t)(n0 % a.R);
+    a.pad1 = 0;
     a.nu = c->cfg.nu;
     a.dt = c->cfg.dt;
     a.c1 = d.c1[0];
@@ -274,6 +277,7 @@ at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int 
 // 3D launcher (at_step3d.hip)
 at_status at3_launch(at_ctx *c, const double *uin, double *uout, int64_t n0, int s, int publish);
 int at3_max_fuse(const at_ctx *c);
+int at3_variants();
 
 // accessors used by the 3D translation unit
 extern "C++" {
@@ -287,6 +291,7 @@ void at_ctx_coefs(const at_ctx *c, double *c1, double *c2)
     for (int a = 0; a < 3; ++a) { c1[a] = c->d.c1[a]; c2[a] = c->d.c2[a]; }
 }
 at_status at_fail(at_status st, const char *msg) { return fail(st, "%s", msg); }
+int at_ctx_variant(const at_ctx *c) { return c->variant; }
 }
 
 namespace {
@@ -369,6 +374,7 @@ at_status at_init(const at_config *cfg, at_ctx **out)
     c->mu = cfg->record ? (double *)(base + L.mu) : nullptr;
     c->gnu = cfg->record ? (double *)(base + L.gnu) : nullptr;
     c->n = 0;
+    c->variant = 0;
     c->fuse = cfg->fuse_steps > 0 ? std::min(cfg->fuse_steps, max_fuse(c)) : 1;
     hipError_t e = hipSuccess;
     if (cfg->delay_mode == AT_DELAY_GENERATE)
@@ -397,6 +403,15 @@ at_status at_set_fuse(at_ctx *c, int32_t s)
     const int mf = max_fuse(c);
     if (s > mf) return fail(AT_ERR_ARG, "fuse_steps %d exceeds the limit %d of this grid", s, mf);
     c->fuse = s;
+    return AT_OK;
+}
+
+at_status at_set_variant(at_ctx *c, int32_t v)
+{
+    if (!c) return fail(AT_ERR_ARG, "null context");
+    const int nv = c->d.dim == 1 ? 1 : at3_variants();
+    if (v < 0 || v >= nv) return fail(AT_ERR_ARG, "variant must be in 0..%d", nv - 1);
+    c->variant = v;
     return AT_OK;
 }
 
@@ -460,21 +475,28 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
     if (trial_steps < 1 || trial_steps > c->cfg.nsteps_max)
         return fail(AT_ERR_ARG, "trial_steps must be in 1..nsteps_max");
     const int mf = max_fuse(c);
-    static const int cands[] = {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32};
+    // 1D: steps per launch; 3D: kernel variant (one step per launch)
+    std::vector<int> cands;
+    if (c->d.dim == 1) {
+        for (int s : {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32})
+            if (s <= mf) cands.push_back(s);
+    } else {
+        for (int v = 0; v < at3_variants(); ++v) cands.push_back(v);
+    }
     hipEvent_t e0, e1;
     AT_HIP(hipEventCreate(&e0));
     AT_HIP(hipEventCreate(&e1));
     float best_ms = 1e30f;
-    int best = 1;
+    int best = cands[0];
     const uint64_t rlev = ring_level_doubles(&c->cfg, c->d);
     for (int s : cands) {
-        if (s > mf) break;
         float ms_best = 1e30f;
         for (int rep = 0; rep < 2; ++rep) {
             AT_HIP(launch_fill(c->ring, (int64_t)c->lay.R * (int64_t)rlev, 0.0, c->st));
             AT_HIP(launch_copy(t1, u0, field_doubles(c), c->st));
             c->n = 0;
-            c->fuse = s;
+            if (c->d.dim == 1) c->fuse = s;
+            else c->variant = s;
             AT_HIP(hipEventRecord(e0, c->st));
             at_status st = at_run(c, t1, t2, trial_steps);
             if (st) { c->n = 0; return st; }
@@ -491,7 +513,8 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
     AT_HIP(launch_fill(c->ring, (int64_t)c->lay.R * (int64_t)rlev, 0.0, c->st));
     AT_HIP(hipStreamSynchronize(c->st));
     c->n = 0;
-    c->fuse = best;
+    if (c->d.dim == 1) c->fuse = best;
+    else c->variant = best;
     if (chosen) *chosen = best;
     return AT_OK;
 }
@@ -596,6 +619,8 @@ at_status at_adjoint(at_ctx *c, const double *lambda_T, double *grad_u0, double 
                 a.Rmu = c->lay.Rmu;
                 a.L = c->cfg.L;
                 a.stale = c->cfg.halo_mode;
+                a.mslot0 = (int32_t)(n % a.Rmu);
+                a.pad0 = 0;
                 a.nu = c->cfg.nu;
                 a.dt = c->cfg.dt;
                 a.c1 = d.c1[0];
@@ -700,6 +725,8 @@ at_status batch_tables(at_batch *b, int slot, int s, double *const *u, double *c
         a.stale = b->cfg[j].halo_mode;
         a.publish = 1;
         a.RL = (int32_t)rg.RL;
+        a.slot0 = 0;          // set per launch by the batched kernel
+        a.pad1 = 0;
         a.nu = b->cfg[j].nu;
         a.dt = b->cfg[j].dt;
         a.c1 = d.c1[0];

@@ -26,6 +26,8 @@ struct Step1D {
     int32_t stale;            // 1: halo = level n-k without extrapolation
     int32_t publish;          // 1: write level n edges to the ring
     int32_t RL;               // left rim of the loaded region (aligned kernel)
+    int32_t slot0;            // n0 mod R (ring slot of level n0)
+    int32_t pad1;
     double nu, dt, c1, c2, cadv;
 };
 
@@ -42,6 +44,8 @@ struct Adj1D {
     int64_t n;
     int64_t nsteps_total;     // steps of the recorded run (gather window bound)
     int32_t R, Rmu, L, stale;
+    int32_t mslot0;           // n mod Rmu
+    int32_t pad0;
     double nu, dt, c1, c2, cadv;
 };
 

@@ -43,6 +43,16 @@ __device__ __forceinline__ int64_t floordiv(int64_t a, int64_t b)
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 
+// ring slot of level n0 + d for d in [-(R-1), R-1] (the levels a launch
+// touches lie within one ring length of n0)
+__device__ __forceinline__ int64_t ring_slot(const Step1D &a, int64_t d)
+{
+    int64_t x = a.slot0 + d;
+    if (x < 0) x += a.R;
+    if (x >= a.R) x -= a.R;
+    return x;
+}
+
 __device__ __forceinline__ double extrap(int kk, bool stale, double v0, double v1, double v2,
                                          int M)
 {
@@ -127,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
         const int64_t n = a.n0 + t;
         // ---- edge points of level n: LDS history for later steps, ring for later launches
         if (has_edge) {
-            const int64_t slot = n % a.R;
+            const int64_t slot = ring_slot(a, t);
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
                 const int rp = rp0 + j;
@@ -208,7 +218,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
                                         if (lev >= a.n0)
                                             vv[jj] = eh[(((int)(lev - a.n0) * a.NT + stl) * 2 + sside) * H + q];
                                         else
-                                            vv[jj] = a.ring[(((lev % a.R) * a.P + stp) * 2 + sside) * H + q];
+                                            vv[jj] = a.ring[((ring_slot(a, lev - a.n0) * a.P + stp) * 2 + sside) * H + q];
                                     }
                                 }
                                 v = extrap(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
@@ -301,7 +311,7 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
 
     for (int t = 0; t < a.s; ++t) {
         const int64_t n = a.n0 + t;
-        const int64_t slot = n % a.R;
+        const int64_t slot = ring_slot(a, t);
         // ---- record this level's tile edges (LDS history; ring when owned)
         if (lo_edge || hi_edge) {
 #pragma unroll
@@ -350,7 +360,7 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
                                 const int64_t lev = n - kk - jj;
                                 vv[jj] = (lev >= a.n0)
                                     ? eh[(((int)(lev - a.n0) * a.NT + stl) * 2 + sside) * H + q]
-                                    : a.ring[(((lev % a.R) * a.P + stp) * 2 + sside) * H + q];
+                                    : a.ring[((ring_slot(a, lev - a.n0) * a.P + stp) * 2 + sside) * H + q];
                             }
                         }
                         const double hv = extrap(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
@@ -401,6 +411,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d_aligned_batch(const Step1D 
     const int2 e = tbl[blockIdx.x];
     Step1D a = descs[e.x];
     a.n0 = n0;
+    a.slot0 = (int32_t)(n0 % a.R);    // once per workgroup (uniform)
     if (flip) {
         const double *t = a.uin;
         a.uin = a.uout;

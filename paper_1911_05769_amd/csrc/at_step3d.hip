@@ -16,11 +16,13 @@
 // faces x-low, x-high, y-low, y-high, z-low, z-high, each [3][plane] with the
 // plane indexed (z, y) for x-faces, (z, x) for y-faces, (y, x) for z-faces.
 //
-// Work decomposition (2.5D): a workgroup of 64 x 4 threads owns a 64 x 16
-// x-y tile and marches through ZC planes in z.  Each thread keeps the z-1, z,
-// z+1 values of its 4 rows (3 components) in registers; the current plane
-// with one-point rims sits in LDS for the x and y neighbours.  Block faces
-// inside the tile are handled per point (any block width >= 2).
+// Work decomposition (2.5D): a workgroup of 64 x 8 threads owns a 64 x 8 x-y
+// tile (one point per thread) and marches through ZC planes in z.  Each
+// thread keeps the z-1, z, z+1 values (3 components) in registers and has
+// planes z+2 and z+3 in flight; the current plane with one-point rims sits in a
+// double-buffered LDS tile for the x and y neighbours (one barrier per
+// plane).  Block faces inside the tile are handled per point (any block
+// width >= 2).
 #include "../../include/at.h"
 #include "at_internal.h"
 
@@ -32,6 +34,7 @@ const int8_t *at_ctx_delays(const at_ctx *c);
 int at_ctx_R(const at_ctx *c);
 hipStream_t at_ctx_stream(const at_ctx *c);
 void at_ctx_coefs(const at_ctx *c, double *c1, double *c2);
+int at_ctx_variant(const at_ctx *c);
 
 namespace atk {
 
@@ -49,161 +52,190 @@ struct Step3D {
     int64_t psz[3];           // plane sizes of x-, y-, z-faces
     int64_t n;
     int32_t R, stale, publish, ZC;
+    int32_t slot0;            // n mod R
+    int32_t pad0;
     double nu, dt, c1[3], c2[3];
 };
 
 namespace {
 
 constexpr int TX = 64;        // tile width in x (one wave64 per row)
-constexpr int TYW = 4;        // waves per workgroup
-constexpr int RY = 4;         // rows per thread
-constexpr int TY = TYW * RY;  // tile height in y
 
-__device__ __forceinline__ int64_t wrapi(int64_t i, int64_t n)
-{
-    return i < 0 ? i + n : (i >= n ? i - n : i);
-}
+__device__ __forceinline__ int wrap32(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// AT halo across face (axis a, side s) of block (bx, by, bz) for component c
-// at face-plane position pos; kk > 0.
-__device__ __forceinline__ double halo3(const Step3D &A, int a, int s, int kk, int64_t bx,
-                                        int64_t by, int64_t bz, int c, int64_t pos)
+// TY rows per tile (= waves per workgroup, one row per thread); PF planes
+// prefetched ahead (1 or 2); MINW waves per SIMD the register budget allows.
+template <int TY, int PF, int MINW>
+__global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
 {
-    int64_t nb[3] = {bx, by, bz};
-    const int64_t Pa = a == 0 ? A.Px : (a == 1 ? A.Py : A.Pz);
-    nb[a] = wrapi(nb[a] + (s ? 1 : -1), Pa);
-    const int64_t b2 = (nb[2] * A.Py + nb[1]) * A.Px + nb[0];
-    const int64_t off = b2 * A.bstride + A.foff[2 * a + (1 - s)] + c * A.psz[a] + pos;
-    const double v0 = A.ring[((A.n - kk) % A.R) * A.level + off];
-    if (A.stale) return v0;
-    const double v1 = A.ring[((A.n - kk - 1) % A.R) * A.level + off];
-    const double dk = (double)kk;
-    return v0 + dk * (v0 - v1);
-}
-
-__global__ __launch_bounds__(TX * TYW) void k_step3d(Step3D A)
-{
-    __shared__ double pl[3][TY + 2][TX + 2];
+    __shared__ double pl[2][3][TY + 2][TX + 2];
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int64_t X0 = (int64_t)blockIdx.x * TX, Y0 = (int64_t)blockIdx.y * TY;
-    const int64_t Z0 = (int64_t)blockIdx.z * A.ZC;
-    const int64_t Z1 = (Z0 + A.ZC < A.nz) ? Z0 + A.ZC : A.nz;
-    const int wx = (int)((A.nx - X0 < TX) ? A.nx - X0 : TX);
-    const int hy = (int)((A.ny - Y0 < TY) ? A.ny - Y0 : TY);
-    const int64_t x = X0 + tx;
-    const bool xin = tx < wx;
-    const int64_t bx = x / A.Wx, lx = x - bx * A.Wx;
-    const int64_t plane = A.nx * A.ny;
+    const int nx = (int)A.nx, ny = (int)A.ny, nz = (int)A.nz;
+    const int X0 = blockIdx.x * TX, Y0 = blockIdx.y * TY;
+    const int Z0 = blockIdx.z * A.ZC;
+    const int Z1 = (Z0 + A.ZC < nz) ? Z0 + A.ZC : nz;
+    const int wx = (nx - X0 < TX) ? nx - X0 : TX;
+    const int hy = (ny - Y0 < TY) ? ny - Y0 : TY;
+    const int x = X0 + tx, y = Y0 + ty;
+    const bool act = tx < wx && ty < hy;
+    const int plane = nx * ny;
+    const int bx = x / A.Wx, lx = x - bx * A.Wx;
+    const int by = y / A.Wy, ly = y - by * A.Wy;
+    const double *U0 = A.uin, *U1 = A.uin + A.npt, *U2 = A.uin + 2 * A.npt;
+    // rim loads of this thread (lanes 0/1: x rims of its row; waves 0/1: y rims)
+    const bool xrim = tx < 2 && ty < hy;
+    const int xs = tx == 0 ? wrap32(X0 - 1, nx) : wrap32(X0 + wx, nx);
+    const int xcol = tx == 0 ? 0 : wx + 1;
+    const bool yrim = ty < 2 && tx < wx;
+    const int ys = ty == 0 ? wrap32(Y0 - 1, ny) : wrap32(Y0 + hy, ny);
+    const int yrow = ty == 0 ? 0 : hy + 1;
+    const int col = y * nx + x;
 
-    double zm[RY][3], zc[RY][3], zp[RY][3];
-    int64_t yr[RY], by[RY], ly[RY];
-    bool rin[RY];
+    auto ld3 = [&](int off, double *v, bool on) {
+        v[0] = on ? U0[off] : 0.0;
+        v[1] = on ? U1[off] : 0.0;
+        v[2] = on ? U2[off] : 0.0;
+    };
+    // register pipeline: planes z-1, z, z+1 in use, z+2 (and z+3 when PF = 2)
+    // in flight; rims of plane z+1 (and z+2) in flight
+    double zm[3], zc[3], zp[3], zq[3], zr[3], rx[3], ry[3], rx2[3], ry2[3];
+    ld3(wrap32(Z0 - 1, nz) * plane + col, zm, act);
+    ld3(Z0 * plane + col, zc, act);
+    ld3(wrap32(Z0 + 1, nz) * plane + col, zp, act);
+    if (PF == 2) ld3(wrap32(Z0 + 2, nz) * plane + col, zq, act && Z0 + 1 < Z1);
+    ld3(Z0 * plane + y * nx + xs, rx, xrim);
+    ld3(Z0 * plane + ys * nx + x, ry, yrim);
+    // plane Z0 into buffer 0
 #pragma unroll
-    for (int r = 0; r < RY; ++r) {
-        const int yy = ty * RY + r;
-        rin[r] = xin && yy < hy;
-        yr[r] = Y0 + yy;
-        by[r] = yr[r] / A.Wy;
-        ly[r] = yr[r] - by[r] * A.Wy;
+    for (int c = 0; c < 3; ++c) {
+        if (act) pl[0][c][ty + 1][tx + 1] = zc[c];
+        if (xrim) pl[0][c][ty + 1][xcol] = rx[c];
+        if (yrim) pl[0][c][yrow][tx + 1] = ry[c];
     }
-    {
-        const int64_t zlo = wrapi(Z0 - 1, A.nz);
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                zm[r][c] = rin[r] ? A.uin[c * A.npt + zlo * plane + yr[r] * A.nx + x] : 0.0;
-                zc[r][c] = rin[r] ? A.uin[c * A.npt + Z0 * plane + yr[r] * A.nx + x] : 0.0;
-            }
+    {   // rims of plane Z0 + 1 (and Z0 + 2)
+        const int zo = wrap32(Z0 + 1, nz) * plane;
+        ld3(zo + y * nx + xs, rx, xrim && Z0 + 1 < Z1);
+        ld3(zo + ys * nx + x, ry, yrim && Z0 + 1 < Z1);
+        if (PF == 2) {
+            const int zo2 = wrap32(Z0 + 2, nz) * plane;
+            ld3(zo2 + y * nx + xs, rx2, xrim && Z0 + 2 < Z1);
+            ld3(zo2 + ys * nx + x, ry2, yrim && Z0 + 2 < Z1);
+        }
     }
     const int8_t *krow = A.delays + A.n * A.F;
-    const int64_t slot = A.n % A.R;
+    const int64_t slot = A.slot0;
 
-    for (int64_t z = Z0; z < Z1; ++z) {
-        const int64_t zn = wrapi(z + 1, A.nz);
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                zp[r][c] = rin[r] ? A.uin[c * A.npt + zn * plane + yr[r] * A.nx + x] : 0.0;
-        // current plane -> LDS, with one-point rims
-#pragma unroll
-        for (int r = 0; r < RY; ++r)
-            if (rin[r])      // only owned cells: the rims are written below
-#pragma unroll
-                for (int c = 0; c < 3; ++c) pl[c][ty * RY + r + 1][tx + 1] = zc[r][c];
-        const int64_t zoff = z * plane;
-        if (tx < 2) {     // x rims of this thread's rows
-            const int64_t xs = tx == 0 ? wrapi(X0 - 1, A.nx) : wrapi(X0 + wx, A.nx);
-            const int col = tx == 0 ? 0 : wx + 1;
-#pragma unroll
-            for (int r = 0; r < RY; ++r)
-                if (ty * RY + r < hy)
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        pl[c][ty * RY + r + 1][col] = A.uin[c * A.npt + zoff + yr[r] * A.nx + xs];
-        }
-        if (ty < 2 && xin) {   // y rims
-            const int64_t ys = ty == 0 ? wrapi(Y0 - 1, A.ny) : wrapi(Y0 + hy, A.ny);
-            const int row = ty == 0 ? 0 : hy + 1;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) pl[c][row][tx + 1] = A.uin[c * A.npt + zoff + ys * A.nx + x];
-        }
+    int bz = Z0 / A.Wz, lz = Z0 - bz * A.Wz;
+    for (int z = Z0; z < Z1; ++z, ++lz) {
+        if (lz == A.Wz) { lz = 0; ++bz; }
+        const int buf = (z - Z0) & 1;
+        const bool more = z + 1 < Z1;
+        if (PF == 2) ld3(wrap32(z + 3, nz) * plane + col, zr, act && z + 2 < Z1);
+        else ld3(wrap32(z + 2, nz) * plane + col, zq, act && more);
         __syncthreads();
-        const int64_t bz = z / A.Wz, lz = z - bz * A.Wz;
-#pragma unroll
-        for (int r = 0; r < RY; ++r) {
-            if (!rin[r]) continue;
-            const int row = ty * RY + r + 1;
-            const int64_t b = (bz * A.Py + by[r]) * A.Px + bx;
-            // delays of the faces this point touches (0 when it touches none)
+        if (act) {
+            const int64_t b = ((int64_t)bz * A.Py + by) * A.Px + bx;
             const int kxl = lx == 0 ? krow[6 * b + 0] : 0;
             const int kxh = lx == A.Wx - 1 ? krow[6 * b + 1] : 0;
-            const int kyl = ly[r] == 0 ? krow[6 * b + 2] : 0;
-            const int kyh = ly[r] == A.Wy - 1 ? krow[6 * b + 3] : 0;
+            const int kyl = ly == 0 ? krow[6 * b + 2] : 0;
+            const int kyh = ly == A.Wy - 1 ? krow[6 * b + 3] : 0;
             const int kzl = lz == 0 ? krow[6 * b + 4] : 0;
             const int kzh = lz == A.Wz - 1 ? krow[6 * b + 5] : 0;
-            const double ux = zc[r][0], uy = zc[r][1], uz = zc[r][2];
+            const int px = lz * A.Wy + ly, py = lz * A.Wx + lx, pz = ly * A.Wx + lx;
+            // neighbours: x/y from the LDS tile, z from registers
+            double nb[6][3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double u = zc[r][c];
-                double xl = pl[c][row][tx], xr = pl[c][row][tx + 2];
-                double yl = pl[c][row - 1][tx + 1], yh = pl[c][row + 1][tx + 1];
-                double zl = zm[r][c], zh = zp[r][c];
-                if (kxl) xl = halo3(A, 0, 0, kxl, bx, by[r], bz, c, lz * A.Wy + ly[r]);
-                if (kxh) xr = halo3(A, 0, 1, kxh, bx, by[r], bz, c, lz * A.Wy + ly[r]);
-                if (kyl) yl = halo3(A, 1, 0, kyl, bx, by[r], bz, c, lz * A.Wx + lx);
-                if (kyh) yh = halo3(A, 1, 1, kyh, bx, by[r], bz, c, lz * A.Wx + lx);
-                if (kzl) zl = halo3(A, 2, 0, kzl, bx, by[r], bz, c, ly[r] * A.Wx + lx);
-                if (kzh) zh = halo3(A, 2, 1, kzh, bx, by[r], bz, c, ly[r] * A.Wx + lx);
+                nb[0][c] = pl[buf][c][ty + 1][tx];
+                nb[1][c] = pl[buf][c][ty + 1][tx + 2];
+                nb[2][c] = pl[buf][c][ty][tx + 1];
+                nb[3][c] = pl[buf][c][ty + 2][tx + 1];
+                nb[4][c] = zm[c];
+                nb[5][c] = zp[c];
+            }
+            // AT halo values across the block faces this point touches
+            const int kf[6] = {kxl, kxh, kyl, kyh, kzl, kzh};
+#pragma unroll
+            for (int f = 0; f < 6; ++f) {
+                const int kk = kf[f];
+                if (kk > 0) {
+                    const int a = f >> 1, sd = f & 1;
+                    int n0 = bx, n1 = by, n2 = bz;
+                    if (a == 0) n0 = wrap32(bx + (sd ? 1 : -1), A.Px);
+                    else if (a == 1) n1 = wrap32(by + (sd ? 1 : -1), A.Py);
+                    else n2 = wrap32(bz + (sd ? 1 : -1), A.Pz);
+                    const int pos = a == 0 ? px : (a == 1 ? py : pz);
+                    const int64_t off = (((int64_t)n2 * A.Py + n1) * A.Px + n0) * A.bstride +
+                                        A.foff[2 * a + (1 - sd)] + pos;
+                    int s0 = A.slot0 - kk, s1 = A.slot0 - kk - 1;     // levels n-k, n-k-1
+                    if (s0 < 0) s0 += A.R;
+                    if (s1 < 0) s1 += A.R;
+                    const double *r0 = A.ring + s0 * A.level + off;
+                    const double *r1 = A.ring + s1 * A.level + off;
+                    const double dk = (double)kk;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const double v0 = r0[c * A.psz[a]];
+                        nb[f][c] = A.stale ? v0 : v0 + dk * (v0 - r1[c * A.psz[a]]);
+                    }
+                }
+            }
+            const double ux = zc[0], uy = zc[1], uz = zc[2];
+            double *out = A.uout + (int64_t)z * plane + col;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double u = zc[c];
+                const double xl = nb[0][c], xr = nb[1][c], yl = nb[2][c], yh = nb[3][c];
+                const double zl = nb[4][c], zh = nb[5][c];
                 const double D1x = (xr - xl) * A.c1[0], D2x = ((xr - 2.0 * u) + xl) * A.c2[0];
                 const double D1y = (yh - yl) * A.c1[1], D2y = ((yh - 2.0 * u) + yl) * A.c2[1];
                 const double D1z = (zh - zl) * A.c1[2], D2z = ((zh - 2.0 * u) + zl) * A.c2[2];
                 const double lap = (D2x + D2y) + D2z;
                 const double adv = (ux * D1x + uy * D1y) + uz * D1z;
-                const double F = A.nu * lap - adv;
-                A.uout[c * A.npt + zoff + yr[r] * A.nx + x] = u + A.dt * F;
+                out[c * A.npt] = u + A.dt * (A.nu * lap - adv);
             }
-            // publish level n values of points on block faces
-            if (A.publish) {
-                const int64_t base = slot * A.level + b * A.bstride;
+            // publish level-n values of points on block faces
+            const bool onface = lx == 0 || lx == A.Wx - 1 || ly == 0 || ly == A.Wy - 1 ||
+                                lz == 0 || lz == A.Wz - 1;
+            if (A.publish && onface) {
+                double *base = A.ring + slot * A.level + b * A.bstride;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const double u = zc[r][c];
-                    if (lx == 0) A.ring[base + A.foff[0] + c * A.psz[0] + lz * A.Wy + ly[r]] = u;
-                    if (lx == A.Wx - 1) A.ring[base + A.foff[1] + c * A.psz[0] + lz * A.Wy + ly[r]] = u;
-                    if (ly[r] == 0) A.ring[base + A.foff[2] + c * A.psz[1] + lz * A.Wx + lx] = u;
-                    if (ly[r] == A.Wy - 1) A.ring[base + A.foff[3] + c * A.psz[1] + lz * A.Wx + lx] = u;
-                    if (lz == 0) A.ring[base + A.foff[4] + c * A.psz[2] + ly[r] * A.Wx + lx] = u;
-                    if (lz == A.Wz - 1) A.ring[base + A.foff[5] + c * A.psz[2] + ly[r] * A.Wx + lx] = u;
+                    const double u = zc[c];
+                    if (lx == 0) base[A.foff[0] + c * A.psz[0] + px] = u;
+                    if (lx == A.Wx - 1) base[A.foff[1] + c * A.psz[0] + px] = u;
+                    if (ly == 0) base[A.foff[2] + c * A.psz[1] + py] = u;
+                    if (ly == A.Wy - 1) base[A.foff[3] + c * A.psz[1] + py] = u;
+                    if (lz == 0) base[A.foff[4] + c * A.psz[2] + pz] = u;
+                    if (lz == A.Wz - 1) base[A.foff[5] + c * A.psz[2] + pz] = u;
                 }
             }
         }
-        __syncthreads();
+        if (more) {
+            // plane z+1 into the other buffer (its readers finished before the barrier)
 #pragma unroll
-        for (int r = 0; r < RY; ++r)
+            for (int c = 0; c < 3; ++c) {
+                if (act) pl[buf ^ 1][c][ty + 1][tx + 1] = zp[c];
+                if (xrim) pl[buf ^ 1][c][ty + 1][xcol] = rx[c];
+                if (yrim) pl[buf ^ 1][c][yrow][tx + 1] = ry[c];
+            }
+            if (PF == 2) {                                            // rims of plane z+3
+                const int zo = wrap32(z + 3, nz) * plane;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) { zm[r][c] = zc[r][c]; zc[r][c] = zp[r][c]; }
+                for (int c = 0; c < 3; ++c) { rx[c] = rx2[c]; ry[c] = ry2[c]; }
+                ld3(zo + y * nx + xs, rx2, xrim && z + 3 < Z1);
+                ld3(zo + ys * nx + x, ry2, yrim && z + 3 < Z1);
+            } else {                                                  // rims of plane z+2
+                const int zo = wrap32(z + 2, nz) * plane;
+                ld3(zo + y * nx + xs, rx, xrim && z + 2 < Z1);
+                ld3(zo + ys * nx + x, ry, yrim && z + 2 < Z1);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            zm[c] = zc[c]; zc[c] = zp[c]; zp[c] = zq[c];
+            if (PF == 2) zq[c] = zr[c];
+        }
     }
 }
 
@@ -226,8 +258,8 @@ at_status at3_check(const at_config *c)
     if (c->order != 2) return at_fail(AT_ERR_ARG, "3D stepper is order 2");
     for (int a = 0; a < 3; ++a)
         if (c->n[a] / c->p[a] < 2) return at_fail(AT_ERR_SHAPE, "3D block narrower than 2");
-    if (c->n[0] * c->n[1] * c->n[2] > ((int64_t)1 << 36))
-        return at_fail(AT_ERR_SHAPE, "3D grid too large");
+    if (c->n[0] * c->n[1] * c->n[2] >= ((int64_t)1 << 31))
+        return at_fail(AT_ERR_SHAPE, "3D grid too large (at most 2^31 - 1 points per component)");
     return AT_OK;
 }
 
@@ -243,6 +275,11 @@ uint64_t at3_ring_level_doubles(const at_config *c)
 }
 
 int at3_max_fuse(const at_ctx *) { return 1; }
+
+// kernel variants the autotuner may choose from (tile rows, prefetch depth,
+// register budget); every variant performs the same operations
+int at3_variants() { return 6; }
+static int k3_rows(int var) { static const int r[6] = {8, 8, 4, 4, 16, 16}; return r[var < 0 || var > 5 ? 0 : var]; }
 
 at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, int s, int publish)
 {
@@ -271,16 +308,27 @@ at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, i
     A.foff[5] = 6 * A.psz[0] + 6 * A.psz[1] + 3 * A.psz[2];
     A.n = n0;
     A.R = at_ctx_R(ctx);
+    A.slot0 = (int32_t)(n0 % A.R);
     A.stale = c->halo_mode;
     A.publish = publish;
     A.nu = c->nu;
     A.dt = c->dt;
     at_ctx_coefs(ctx, A.c1, A.c2);
-    const int64_t gx = (A.nx + TX - 1) / TX, gy = (A.ny + TY - 1) / TY;
+    const int var = at_ctx_variant(ctx);
+    const int TYv = k3_rows(var);
+    const int64_t gx = (A.nx + TX - 1) / TX, gy = (A.ny + TYv - 1) / TYv;
     A.ZC = zchunk(A.nz, gx * gy);
     const int64_t gz = (A.nz + A.ZC - 1) / A.ZC;
-    hipLaunchKernelGGL(k_step3d, dim3((unsigned)gx, (unsigned)gy, (unsigned)gz), dim3(TX, TYW),
-                       0, at_ctx_stream(ctx), A);
+    const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)gz), block(TX, TYv);
+    hipStream_t st = at_ctx_stream(ctx);
+    switch (var) {
+    case 0: hipLaunchKernelGGL((k_step3d<8, 1, 4>), grid, block, 0, st, A); break;
+    case 1: hipLaunchKernelGGL((k_step3d<8, 2, 4>), grid, block, 0, st, A); break;
+    case 2: hipLaunchKernelGGL((k_step3d<4, 2, 4>), grid, block, 0, st, A); break;
+    case 3: hipLaunchKernelGGL((k_step3d<4, 2, 3>), grid, block, 0, st, A); break;
+    case 4: hipLaunchKernelGGL((k_step3d<16, 1, 2>), grid, block, 0, st, A); break;
+    default: hipLaunchKernelGGL((k_step3d<16, 2, 2>), grid, block, 0, st, A); break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return at_fail(AT_ERR_HIP, hipGetErrorString(e));
     return AT_OK;

@@ -74,6 +74,24 @@ def test_parity_3d(gpu, case):
     assert err <= TOL
 
 
+def test_every_kernel_variant_same_bits(gpu):
+    n, p, L, nu, nst = (96, 40, 36), (4, 5, 3), 3, 0.01, 21
+    u0 = I.u0_modes3d(n, 6, 3, 8)
+    dt = I.dt_rule(2 * math.pi / max(n), float(np.max(np.abs(u0))), nu)
+    outs = []
+    for v in range(6):
+        st = gpu.Stepper(dim=3, n=n, p=p, order=2, L=L, nu=nu, dt=dt, nsteps_max=nst, seed=3)
+        st.set_variant(v)
+        u, s = dev(u0), torch.empty(u0.shape, dtype=torch.float64, device="cuda")
+        st.run(u, s, nst)
+        outs.append(host(u))
+        k = st.delays()
+    ref = oracle.run3d(u0, n, p, L, nu, dt, k, nst)
+    for v, o in enumerate(outs):
+        assert relerr(o, ref) <= TOL, "variant %d" % v
+        assert np.array_equal(o, outs[0]), "variant %d differs" % v
+
+
 def test_full_size_3d_first_steps(gpu):
     """512^3 x 3 components, 8^3 blocks of 64^3, L = 3: the first 4 steps on the
     whole grid against the oracle (the start-up clamp allows delays from
