@@ -142,9 +142,12 @@ at_status at_run(at_ctx *ctx, double *u, double *scratch, int64_t nsteps);
 at_status at_autotune(at_ctx *ctx, const double *u0, double *t1, double *t2,
                       int32_t trial_steps, int32_t *chosen);
 
-/* Kernel variant of a 3D context: 0..5 select the tile height, prefetch
- * depth and register budget of the 3D stepper (results are bit-identical for
- * every variant; at_autotune picks one for 3D contexts).  1D contexts accept
+/* Kernel variant of a 3D context (results are bit-identical for every
+ * variant; at_autotune picks one for 3D contexts): 0..5 LDS-tiled with
+ * per-point halos (tile rows, prefetch depth, register budget), 6..8 and
+ * 12..14 LDS-tiled with halos in the tile rims and 1 to 4 planes prefetched
+ * (block widths multiples of the tile, AT_ERR_ARG otherwise), 9..11
+ * barrier-free column march.  1D contexts accept
  * only 0. */
 at_status at_set_variant(at_ctx *ctx, int32_t variant);
 

@@ -87,12 +87,24 @@ __global__ __launch_bounds__(kThreads) void k_adj1d(Adj1D a)
     const Partials<ORDER> pd = partials<ORDER>(a.c1, a.c2);
     const bool stale = a.stale != 0;
 
-    for (int r = tid; r < owned + 2 * H; r += kThreads) {
-        int64_t g = c0 - H + r;
-        if (g < 0) g += a.N;
-        if (g >= a.N) g -= a.N;
-        sl[r] = a.lam_in[g];
-        su[r] = a.u[g];
+    // all loads issued before the first use (one round trip, not one per pass)
+    double vl[kPPA + 1], vu[kPPA + 1];
+#pragma unroll
+    for (int it = 0; it <= kPPA; ++it) {
+        const int r = it * kThreads + tid;
+        vl[it] = vu[it] = 0.0;
+        if (r < owned + 2 * H) {
+            int64_t g = c0 - H + r;
+            if (g < 0) g += a.N;
+            if (g >= a.N) g -= a.N;
+            vl[it] = a.lam_in[g];
+            vu[it] = a.u[g];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it <= kPPA; ++it) {
+        const int r = it * kThreads + tid;
+        if (r < owned + 2 * H) { sl[r] = vl[it]; su[r] = vu[it]; }
     }
     __syncthreads();
 
@@ -121,12 +133,21 @@ __global__ __launch_bounds__(kThreads) void k_adj1d(Adj1D a)
     };
 
     Acc gacc{0.0, 0.0};
+    const int W32 = (int)a.W;
+    // tile index and offset of this thread's first point; later points step by kThreads
+    const int64_t g0 = c0 + tid;
+    int64_t t = g0 / a.W;
+    int o_ = (int)(g0 - t * a.W);
+#pragma unroll
     for (int it = 0; it < kPPA; ++it) {
         const int l = it * kThreads + tid;
+        if (it > 0) {                       // advance by kThreads points without dividing
+            o_ += kThreads;
+            while (o_ >= W32) { o_ -= W32; ++t; }
+        }
         if (l >= owned) break;
         const int64_t g = c0 + l;
-        const int64_t t = g / a.W;
-        const int64_t o = g - t * a.W;
+        const int64_t o = o_;
         const int r = l + H;
         const double u = su[r];
         // neighbours at level n, AT halo where the stencil leaves the tile

@@ -203,7 +203,7 @@ at_status make_layout(const at_config *c, const Derived &d, Layout &L)
     return AT_OK;
 }
 
-Region1D region_1d(const Derived &d, int s);
+Region1D region_1d(const Derived &d, int s, bool allow_plain = true);
 
 // Largest steps-per-launch usable for this 1D configuration: the owned chunk
 // stays at least half the region (or the whole grid) and the LDS edge
@@ -221,9 +221,13 @@ int max_fuse_1d(const Derived &d)
     return best;
 }
 
-Region1D region_1d(const Derived &d, int s)
+Region1D region_1d(const Derived &d, int s, bool allow_plain)
 {
-    const int ppt = step1d_points_per_thread();
+    // single steps use the 8-point-per-thread kernel when the tiles allow it
+    // (not in the batched form, whose kernel keeps 16 points per thread)
+    const int pplain = step1d_plain_points_per_thread();
+    const bool plain = allow_plain && s == 1 && d.W % pplain == 0;
+    const int ppt = plain ? pplain : step1d_points_per_thread();
     const int64_t reg = (int64_t)kThreads * ppt;
     Region1D r;
     r.aligned = d.W % ppt == 0;
@@ -238,7 +242,8 @@ Region1D region_1d(const Derived &d, int s)
     return r;
 }
 
-at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int s, int publish)
+at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int s, int publish,
+                    double *levels = nullptr)
 {
     const Derived &d = c->d;
     const int reg = kThreads * step1d_points_per_thread();
@@ -262,6 +267,8 @@ at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int 
     a.RL = (int32_t)rg.RL;
     a.slot0 = (int32_t)(n0 % a.R);
     a.pad1 = 0;
+    a.levels = levels;
+    if (levels && !rg.aligned) return fail(AT_ERR_STATE, "level store needs the aligned layout");
     a.nu = c->cfg.nu;
     a.dt = c->cfg.dt;
     a.c1 = d.c1[0];
@@ -278,6 +285,7 @@ at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int 
 at_status at3_launch(at_ctx *c, const double *uin, double *uout, int64_t n0, int s, int publish);
 int at3_max_fuse(const at_ctx *c);
 int at3_variants();
+bool at3_variant_ok(const at_config *c, int var);
 
 // accessors used by the 3D translation unit
 extern "C++" {
@@ -411,6 +419,8 @@ at_status at_set_variant(at_ctx *c, int32_t v)
     if (!c) return fail(AT_ERR_ARG, "null context");
     const int nv = c->d.dim == 1 ? 1 : at3_variants();
     if (v < 0 || v >= nv) return fail(AT_ERR_ARG, "variant must be in 0..%d", nv - 1);
+    if (c->d.dim == 3 && !at3_variant_ok(&c->cfg, v))
+        return fail(AT_ERR_ARG, "variant %d needs block widths that are multiples of its tile", v);
     c->variant = v;
     return AT_OK;
 }
@@ -481,7 +491,8 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
         for (int s : {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32})
             if (s <= mf) cands.push_back(s);
     } else {
-        for (int v = 0; v < at3_variants(); ++v) cands.push_back(v);
+        for (int v = 0; v < at3_variants(); ++v)
+            if (at3_variant_ok(&c->cfg, v)) cands.push_back(v);
     }
     hipEvent_t e0, e1;
     AT_HIP(hipEventCreate(&e0));
@@ -597,9 +608,16 @@ at_status at_adjoint(at_ctx *c, const double *lambda_T, double *grad_u0, double 
         for (int64_t a0 = ((nend - 1) / C) * C; a0 >= 0; a0 -= C) {
             const int64_t a1 = std::min(a0 + C, nend);
             AT_HIP(launch_copy(c->seg, c->ckpt + (a0 / C) * N, N, c->st));
-            for (int64_t n = a0; n + 1 < a1; ++n) {
-                at_status st = launch_1d(c, c->seg + (n - a0) * N, c->seg + (n + 1 - a0) * N, n, 1, 0);
+            // rebuild levels a0+1 .. a1-1: fused launches that also store every
+            // intermediate level (aligned layout), else one launch per step
+            const bool fused = region_1d(d, 2).aligned;
+            const int sr = fused ? std::min(16, max_fuse(c)) : 1;
+            for (int64_t n = a0; n + 1 < a1;) {
+                const int s = (int)std::min<int64_t>(sr, a1 - 1 - n);
+                at_status st = launch_1d(c, c->seg + (n - a0) * N, c->seg + (n + s - a0) * N, n, s,
+                                         0, s > 1 ? c->seg + (n - a0) * N : nullptr);
                 if (st) return st;
+                n += s;
             }
             for (int64_t n = a1 - 1; n >= a0; --n) {
                 Adj1D a;
@@ -708,7 +726,7 @@ at_status batch_tables(at_batch *b, int slot, int s, double *const *u, double *c
     size_t lds = 0;
     for (int j = 0; j < b->count; ++j) {
         const Derived &d = b->d[j];
-        const Region1D rg = region_1d(d, s);
+        const Region1D rg = region_1d(d, s, false);
         Step1D &a = D[j];
         a.uin = u[j];
         a.uout = scr[j];
@@ -727,6 +745,7 @@ at_status batch_tables(at_batch *b, int slot, int s, double *const *u, double *c
         a.RL = (int32_t)rg.RL;
         a.slot0 = 0;          // set per launch by the batched kernel
         a.pad1 = 0;
+        a.levels = nullptr;
         a.nu = b->cfg[j].nu;
         a.dt = b->cfg[j].dt;
         a.c1 = d.c1[0];
@@ -806,7 +825,8 @@ static at_status batch_layout(const at_config *cfgs, int32_t count, std::vector<
         off_ring[j] = off;
         off = align_up(off + 8ull * (uint64_t)Rs[j] * (uint64_t)ds[j].P * 2 * ds[j].h);
         int64_t chmin = ds[j].N;
-        for (int s = 1; s <= smax; ++s) chmin = std::min<int64_t>(chmin, region_1d(ds[j], s).CH);
+        for (int s = 1; s <= smax; ++s)
+            chmin = std::min<int64_t>(chmin, region_1d(ds[j], s, false).CH);
         tbl_cap += (ds[j].N + chmin - 1) / chmin;
     }
     off_desc = off;

@@ -28,6 +28,7 @@ struct Step1D {
     int32_t RL;               // left rim of the loaded region (aligned kernel)
     int32_t slot0;            // n0 mod R (ring slot of level n0)
     int32_t pad1;
+    double *levels;           // optional: levels n0+1 .. n0+s-1 stored at levels + t*N (aligned kernel)
     double nu, dt, c1, c2, cadv;
 };
 
@@ -86,6 +87,7 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
 size_t step1d_lds_bytes(int order, int s, int NT);
 int step1d_points_per_thread();
+int step1d_plain_points_per_thread();
 hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned,
                          int64_t nblocks, hipStream_t st);
 hipError_t launch_step1d_batch(const Step1D *descs, const int2 *tbl, int64_t nblocks, int order,

@@ -35,7 +35,8 @@ namespace atk {
 
 namespace {
 
-constexpr int kPPT = 16;   // region points per thread
+constexpr int kPPT = 16;      // region points per thread (fused and general kernels)
+constexpr int kPPTPlain = 8;  // region points per thread of the single-step kernel
 
 __device__ __forceinline__ int64_t floordiv(int64_t a, int64_t b)
 {
@@ -253,12 +254,13 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
 // part of its register window, a thread that ends a tile its right ones, and
 // then every point runs the same stencil (the split of section 5.2); the
 // window slots replaced belong to this thread alone.
-template <int ORDER, bool LINEAR>
+// FUSED = false: exactly one step per launch (every delayed level comes from
+// the ring; no LDS edge history)
+template <int ORDER, bool LINEAR, bool FUSED = true, int PPT = kPPT>
 __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chunk)
 {
     constexpr int H = ORDER / 2;
     constexpr int M = (ORDER == 2) ? 2 : 3;
-    constexpr int PPT = kPPT;
     extern __shared__ double lds[];
     double *stage = lds;                                  // [kThreads*PPT + kThreads]
     double *xch = lds;                                    // [2][kThreads][2H]  (aliases stage)
@@ -267,7 +269,8 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     const int tid = threadIdx.x;
     const int64_t c0 = chunk * a.CH;
     const int owned = (int)((a.N - c0 < a.CH) ? (a.N - c0) : a.CH);
-    const int sh = a.s * H;
+    const int S = FUSED ? a.s : 1;
+    const int sh = S * H;
     const int E = a.RL + owned + sh;                      // region length (<= kThreads*PPT)
     const int64_t G0 = c0 - a.RL;                         // unwrapped start, multiple of PPT
     int64_t G0w = G0 % a.N;
@@ -309,7 +312,7 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     const bool owns = rp0 >= a.RL && rp0 < a.RL + owned;
     const int64_t F = 2 * a.P;
 
-    for (int t = 0; t < a.s; ++t) {
+    for (int t = 0; t < S; ++t) {
         const int64_t n = a.n0 + t;
         const int64_t slot = ring_slot(a, t);
         // ---- record this level's tile edges (LDS history; ring when owned)
@@ -317,11 +320,11 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
 #pragma unroll
             for (int q = 0; q < H; ++q) {
                 if (lo_edge) {
-                    if (t < a.s - 1) eh[((t * a.NT + tl0) * 2 + 0) * H + q] = w[H + q];
+                    if (FUSED && t < S - 1) eh[((t * a.NT + tl0) * 2 + 0) * H + q] = w[H + q];
                     if (a.publish && owns) a.ring[((slot * a.P + tp0) * 2 + 0) * H + q] = w[H + q];
                 }
                 if (hi_edge) {
-                    if (t < a.s - 1) eh[((t * a.NT + tl0) * 2 + 1) * H + q] = w[PPT + q];
+                    if (FUSED && t < S - 1) eh[((t * a.NT + tl0) * 2 + 1) * H + q] = w[PPT + q];
                     if (a.publish && owns) a.ring[((slot * a.P + tp0) * 2 + 1) * H + q] = w[PPT + q];
                 }
             }
@@ -358,7 +361,7 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
                         for (int jj = 0; jj < M; ++jj) {
                             if (jj == 0 || !a.stale) {
                                 const int64_t lev = n - kk - jj;
-                                vv[jj] = (lev >= a.n0)
+                                vv[jj] = (FUSED && lev >= a.n0)
                                     ? eh[(((int)(lev - a.n0) * a.NT + stl) * 2 + sside) * H + q]
                                     : a.ring[((ring_slot(a, lev - a.n0) * a.P + stp) * 2 + sside) * H + q];
                             }
@@ -381,6 +384,13 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
         }
 #pragma unroll
         for (int j = 0; j < PPT; ++j) w[H + j] = res[j];
+        // every intermediate level of the owned points, straight from registers
+        // (used to rebuild a checkpoint segment for the adjoint)
+        if (FUSED && a.levels && owns && t + 1 < S) {
+            double *dst = a.levels + (int64_t)(t + 1) * a.N + c0 + (rp0 - a.RL);
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) dst[j] = w[H + j];
+        }
     }
 
     __syncthreads();
@@ -398,6 +408,14 @@ template <int ORDER, bool LINEAR>
 __global__ __launch_bounds__(kThreads) void k_step1d_aligned(Step1D a)
 {
     step1d_aligned_body<ORDER, LINEAR>(a, blockIdx.x);
+}
+
+// one step per launch (the plain form): 8 points per thread, a smaller
+// workgroup footprint and more workgroups in flight
+template <int ORDER, bool LINEAR>
+__global__ __launch_bounds__(kThreads) void k_step1d_plain(Step1D a)
+{
+    step1d_aligned_body<ORDER, LINEAR, false, kPPTPlain>(a, blockIdx.x);
 }
 
 // Batched form: workgroup b advances chunk tbl[b].y of instance tbl[b].x;
@@ -563,6 +581,7 @@ int grid_for(int64_t n)
 }  // namespace
 
 int step1d_points_per_thread() { return kPPT; }
+int step1d_plain_points_per_thread() { return kPPTPlain; }
 
 size_t step1d_lds_bytes(int order, int s, int NT)
 {
@@ -575,8 +594,23 @@ size_t step1d_lds_bytes(int order, int s, int NT)
 hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned,
                          int64_t nblocks, hipStream_t st)
 {
-    const size_t lds = step1d_lds_bytes(order, a.s, a.NT);
+    size_t lds = step1d_lds_bytes(order, a.s, a.NT);
+    if (aligned && a.s == 1) {
+        const size_t stage = (size_t)kThreads * kPPTPlain + kThreads;
+        const size_t xch = (size_t)2 * kThreads * order;
+        lds = 8 * (stage > xch ? stage : xch);
+    }
     dim3 grid((unsigned)nblocks), block(kThreads);
+    if (aligned && a.s == 1) {
+        if (order == 2) {
+            if (linear) hipLaunchKernelGGL((k_step1d_plain<2, true>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_step1d_plain<2, false>), grid, block, lds, st, a);
+        } else {
+            if (linear) hipLaunchKernelGGL((k_step1d_plain<4, true>), grid, block, lds, st, a);
+            else hipLaunchKernelGGL((k_step1d_plain<4, false>), grid, block, lds, st, a);
+        }
+        return hipGetLastError();
+    }
     if (aligned) {
         if (order == 2) {
             if (linear) hipLaunchKernelGGL((k_step1d_aligned<2, true>), grid, block, lds, st, a);

@@ -126,6 +126,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
     const int64_t slot = A.slot0;
 
     int bz = Z0 / A.Wz, lz = Z0 - bz * A.Wz;
+    int kbz = -1, kc[6] = {0, 0, 0, 0, 0, 0};
     for (int z = Z0; z < Z1; ++z, ++lz) {
         if (lz == A.Wz) { lz = 0; ++bz; }
         const int buf = (z - Z0) & 1;
@@ -135,12 +136,18 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
         __syncthreads();
         if (act) {
             const int64_t b = ((int64_t)bz * A.Py + by) * A.Px + bx;
-            const int kxl = lx == 0 ? krow[6 * b + 0] : 0;
-            const int kxh = lx == A.Wx - 1 ? krow[6 * b + 1] : 0;
-            const int kyl = ly == 0 ? krow[6 * b + 2] : 0;
-            const int kyh = ly == A.Wy - 1 ? krow[6 * b + 3] : 0;
-            const int kzl = lz == 0 ? krow[6 * b + 4] : 0;
-            const int kzh = lz == A.Wz - 1 ? krow[6 * b + 5] : 0;
+            if (bz != kbz) {          // face delays of this block: reloaded only at block changes
+                kbz = bz;
+                kc[0] = lx == 0 ? krow[6 * b + 0] : 0;
+                kc[1] = lx == A.Wx - 1 ? krow[6 * b + 1] : 0;
+                kc[2] = ly == 0 ? krow[6 * b + 2] : 0;
+                kc[3] = ly == A.Wy - 1 ? krow[6 * b + 3] : 0;
+                kc[4] = krow[6 * b + 4];
+                kc[5] = krow[6 * b + 5];
+            }
+            const int kxl = kc[0], kxh = kc[1], kyl = kc[2], kyh = kc[3];
+            const int kzl = lz == 0 ? kc[4] : 0;
+            const int kzh = lz == A.Wz - 1 ? kc[5] : 0;
             const int px = lz * A.Wy + ly, py = lz * A.Wx + lx, pz = ly * A.Wx + lx;
             // neighbours: x/y from the LDS tile, z from registers
             double nb[6][3];
@@ -239,6 +246,339 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
     }
 }
 
+
+// Aligned variant: block widths are multiples of the tile (Wx % 64 == 0,
+// Wy % TY == 0), so block faces can only lie on the tile's rims (x, y) or on
+// whole planes (z).  Wave 0 computes the x-rim halo values of the next plane
+// (lanes 0..2TY-1), waves 0 and 1 the y-rim rows, and every thread the z
+// neighbour of the next plane, all one plane ahead; the AT value replaces the
+// raw neighbour in the LDS rim (or the z register) and every point then runs
+// the same branch-free stencil (the split of section 5.2).
+template <int TY, int MINW, int PF>
+__global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
+{
+    __shared__ double pl[2][3][TY + 2][TX + 2];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int nx = (int)A.nx, ny = (int)A.ny, nz = (int)A.nz;
+    const int X0 = blockIdx.x * TX, Y0 = blockIdx.y * TY;
+    const int Z0 = blockIdx.z * A.ZC;
+    const int Z1 = (Z0 + A.ZC < nz) ? Z0 + A.ZC : nz;
+    const int x = X0 + tx, y = Y0 + ty;
+    const int plane = nx * ny;
+    const int col = y * nx + x;
+    const int Wx = A.Wx, Wy = A.Wy, Wz = A.Wz;
+    const int bx = X0 / Wx, by = Y0 / Wy;             // one block per tile in x and y
+    const int lx = x - bx * Wx, ly = y - by * Wy;
+    const bool fxl = X0 % Wx == 0, fxh = (X0 + TX) % Wx == 0;    // tile edges on block faces
+    const bool fyl = Y0 % Wy == 0, fyh = (Y0 + TY) % Wy == 0;
+    const double *const U0 = A.uin;
+    auto U = [&](int c, int off) -> double { return U0[(int64_t)c * A.npt + off]; };
+    const int8_t *krow = A.delays + A.n * A.F;
+    int sl0 = A.slot0;
+    auto lvl = [&](int back) -> int64_t { int q = sl0 - back; if (q < 0) q += A.R; return (int64_t)q * A.level; };
+    auto blk = [&](int bxx, int byy, int bzz) -> int64_t {
+        return ((int64_t)bzz * A.Py + byy) * A.Px + bxx;
+    };
+    // roles
+    const bool xr_role = ty == 0 && tx < 2 * TY;
+    const int xr_row = tx >> 1, xr_side = tx & 1;
+    const int xr_x = xr_side ? wrap32(X0 + TX, nx) : wrap32(X0 - 1, nx);
+    const int xr_ly = (Y0 + xr_row) - by * Wy;
+    const bool xr_face = xr_side ? fxh : fxl;
+    const bool yr_role = ty < 2;
+    const int yr_y = ty ? wrap32(Y0 + TY, ny) : wrap32(Y0 - 1, ny);
+    const bool yr_face = ty ? fyh : fyl;
+    const int yr_row = ty ? TY + 1 : 0;
+    const int xr_col = xr_side ? TX + 1 : 0;
+    const int nbx = wrap32(bx + (xr_side ? 1 : -1), A.Px);
+    const int nby = wrap32(by + (ty ? 1 : -1), A.Py);
+
+    // loads of one plane's rims and z neighbour ("issue"), finished later
+    double xv0[3], xv1[3], yv0[3], yv1[3], zv0[3], zv1[3];
+    int xk = 0, yk = 0, zk = 0, zside = 0;
+    int kbz = -1, kc[6] = {0, 0, 0, 0, 0, 0};   // face delays of the current z-block
+    auto issue = [&](int p) {
+        const int bz = p / Wz, lz = p - bz * Wz;
+        const int64_t b = blk(bx, by, bz);
+        if (bz != kbz) {
+            kbz = bz;
+#pragma unroll
+            for (int f = 0; f < 6; ++f) kc[f] = krow[6 * b + f];
+        }
+        if (xr_role) {
+            xk = xr_face ? kc[xr_side] : 0;
+            if (xk > 0) {
+                const int64_t off = blk(nbx, by, bz) * A.bstride + A.foff[1 - xr_side] +
+                                    lz * Wy + xr_ly;
+                const int64_t o0 = lvl(xk) + off, o1 = lvl(xk + 1) + off;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    xv0[c] = A.ring[o0 + c * A.psz[0]];
+                    xv1[c] = A.stale ? 0.0 : A.ring[o1 + c * A.psz[0]];
+                }
+            } else {
+                const int o = p * plane + (Y0 + xr_row) * nx + xr_x;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) xv0[c] = U(c, o);
+            }
+        }
+        if (yr_role) {
+            yk = yr_face ? kc[2 + ty] : 0;
+            if (yk > 0) {
+                const int64_t off = blk(bx, nby, bz) * A.bstride + A.foff[2 + (1 - ty)] +
+                                    lz * Wx + lx;
+                const int64_t o0 = lvl(yk) + off, o1 = lvl(yk + 1) + off;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    yv0[c] = A.ring[o0 + c * A.psz[1]];
+                    yv1[c] = A.stale ? 0.0 : A.ring[o1 + c * A.psz[1]];
+                }
+            } else {
+                const int o = p * plane + yr_y * nx + x;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) yv0[c] = U(c, o);
+            }
+        }
+        // z neighbour across a block face of plane p
+        zk = 0;
+        zside = lz == 0 ? 0 : 1;
+        if (lz == 0 || lz == Wz - 1) zk = kc[4 + zside];
+        if (zk > 0) {
+            const int nbz = wrap32(bz + (zside ? 1 : -1), A.Pz);
+            const int64_t off = blk(bx, by, nbz) * A.bstride + A.foff[4 + (1 - zside)] +
+                                ly * Wx + lx;
+            const int64_t o0 = lvl(zk) + off, o1 = lvl(zk + 1) + off;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                zv0[c] = A.ring[o0 + c * A.psz[2]];
+                zv1[c] = A.stale ? 0.0 : A.ring[o1 + c * A.psz[2]];
+            }
+        }
+    };
+    auto ext = [&](int kk, double v0, double v1) -> double {
+        return A.stale ? v0 : v0 + (double)kk * (v0 - v1);
+    };
+    // finish plane p's rims into LDS buffer bf
+    auto finish_rims = [&](int bf) {
+        if (xr_role)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                pl[bf][c][xr_row + 1][xr_col] = xk > 0 ? ext(xk, xv0[c], xv1[c]) : xv0[c];
+        if (yr_role)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                pl[bf][c][yr_row][tx + 1] = yk > 0 ? ext(yk, yv0[c], yv1[c]) : yv0[c];
+    };
+
+    // register queue: zq[0] = plane z+1, ..., zq[PF] = plane z+1+PF (in flight)
+    double zm[3], zc[3], zq[PF + 1][3], hz[3];
+    bool hz_lo = false, hz_hi = false;      // plane's z neighbour replaced by hz (low / high)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        zm[c] = U(c, wrap32(Z0 - 1, nz) * plane + col);
+        zc[c] = U(c, Z0 * plane + col);
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+            zq[q][c] = (q == 0 || Z0 + q < Z1) ? U(c, wrap32(Z0 + 1 + q, nz) * plane + col) : 0.0;
+    }
+    issue(Z0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pl[0][c][ty + 1][tx + 1] = zc[c];
+    finish_rims(0);
+    if (zk > 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) hz[c] = ext(zk, zv0[c], zv1[c]);
+        hz_lo = zside == 0;
+        hz_hi = zside == 1;
+    }
+    if (Z0 + 1 < Z1) issue(Z0 + 1);
+    const int64_t slot = A.slot0;
+
+    int bz = Z0 / Wz, lz = Z0 - bz * Wz;
+    for (int z = Z0; z < Z1; ++z, ++lz) {
+        if (lz == Wz) { lz = 0; ++bz; }
+        const int buf = (z - Z0) & 1;
+        const bool more = z + 1 < Z1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            zq[PF][c] = z + PF < Z1 ? U(c, wrap32(z + 1 + PF, nz) * plane + col) : 0.0;
+        __syncthreads();
+        const double ux = zc[0], uy = zc[1], uz = zc[2];
+        double *out = A.uout + (int64_t)z * plane + col;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double u = zc[c];
+            const double xl = pl[buf][c][ty + 1][tx], xr = pl[buf][c][ty + 1][tx + 2];
+            const double yl = pl[buf][c][ty][tx + 1], yh = pl[buf][c][ty + 2][tx + 1];
+            const double zl = hz_lo ? hz[c] : zm[c];
+            const double zh = hz_hi ? hz[c] : zq[0][c];
+            const double D1x = (xr - xl) * A.c1[0], D2x = ((xr - 2.0 * u) + xl) * A.c2[0];
+            const double D1y = (yh - yl) * A.c1[1], D2y = ((yh - 2.0 * u) + yl) * A.c2[1];
+            const double D1z = (zh - zl) * A.c1[2], D2z = ((zh - 2.0 * u) + zl) * A.c2[2];
+            const double lap = (D2x + D2y) + D2z;
+            const double adv = (ux * D1x + uy * D1y) + uz * D1z;
+            out[c * A.npt] = u + A.dt * (A.nu * lap - adv);
+        }
+        // publish level-n values of points on block faces
+        if (A.publish && (lx == 0 || lx == Wx - 1 || ly == 0 || ly == Wy - 1 || lz == 0 ||
+                          lz == Wz - 1)) {
+            double *base = A.ring + slot * A.level + blk(bx, by, bz) * A.bstride;
+            const int px = lz * Wy + ly, py = lz * Wx + lx, pz = ly * Wx + lx;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double u = zc[c];
+                if (lx == 0) base[A.foff[0] + c * A.psz[0] + px] = u;
+                if (lx == Wx - 1) base[A.foff[1] + c * A.psz[0] + px] = u;
+                if (ly == 0) base[A.foff[2] + c * A.psz[1] + py] = u;
+                if (ly == Wy - 1) base[A.foff[3] + c * A.psz[1] + py] = u;
+                if (lz == 0) base[A.foff[4] + c * A.psz[2] + pz] = u;
+                if (lz == Wz - 1) base[A.foff[5] + c * A.psz[2] + pz] = u;
+            }
+        }
+        if (more) {
+            // plane z+1: interior, rims and z neighbour (loads issued one plane ago)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pl[buf ^ 1][c][ty + 1][tx + 1] = zq[0][c];
+            finish_rims(buf ^ 1);
+            hz_lo = hz_hi = false;
+            if (zk > 0) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) hz[c] = ext(zk, zv0[c], zv1[c]);
+                hz_lo = zside == 0;
+                hz_hi = zside == 1;
+            }
+            if (z + 2 < Z1) issue(z + 2);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            zm[c] = zc[c];
+            zc[c] = zq[0][c];
+#pragma unroll
+            for (int q = 0; q < PF; ++q) zq[q][c] = zq[q + 1][c];
+        }
+    }
+}
+
+// Barrier-free variant: every thread marches its (x, y) column through the
+// z range with the z-1, z, z+1 values in registers (plane z+2 in flight) and
+// reads its x and y neighbours straight from global memory (L1/L2 hits: the
+// same rows are the neighbouring threads' own loads).  No LDS, no barrier, so
+// each wave advances on its own and many loads are in flight per wave.
+template <int TY>
+__global__ __launch_bounds__(TX * TY) void k_step3d_direct(Step3D A)
+{
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int nx = (int)A.nx, ny = (int)A.ny, nz = (int)A.nz;
+    const int X0 = blockIdx.x * TX, Y0 = blockIdx.y * TY;
+    const int Z0 = blockIdx.z * A.ZC;
+    const int Z1 = (Z0 + A.ZC < nz) ? Z0 + A.ZC : nz;
+    const int x = X0 + tx, y = Y0 + ty;
+    if (x >= nx || y >= ny) return;            // no barrier below: idle threads may leave
+    const int plane = nx * ny;
+    const int col = y * nx + x;
+    const int xm = (x == 0 ? nx : x) - 1, xp = (x + 1 == nx ? 0 : x + 1);
+    const int ym = (y == 0 ? ny : y) - 1, yp = (y + 1 == ny ? 0 : y + 1);
+    const int bx = x / A.Wx, lx = x - bx * A.Wx;
+    const int by = y / A.Wy, ly = y - by * A.Wy;
+    const double *U0 = A.uin;
+    auto U = [&](int c, int off) -> double { return U0[(int64_t)c * A.npt + off]; };
+    double zm[3], zc[3], zp[3], zq[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        zm[c] = U(c, wrap32(Z0 - 1, nz) * plane + col);
+        zc[c] = U(c, Z0 * plane + col);
+        zp[c] = U(c, wrap32(Z0 + 1, nz) * plane + col);
+    }
+    const int8_t *krow = A.delays + A.n * A.F;
+    const int64_t slot = A.slot0;
+    int bz = Z0 / A.Wz, lz = Z0 - bz * A.Wz;
+    int kbz = -1, kc[6] = {0, 0, 0, 0, 0, 0};
+    for (int z = Z0; z < Z1; ++z, ++lz) {
+        if (lz == A.Wz) { lz = 0; ++bz; }
+        const bool more = z + 1 < Z1;
+        const int po = z * plane;
+        double nb[6][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            zq[c] = more ? U(c, wrap32(z + 2, nz) * plane + col) : 0.0;
+            nb[0][c] = U(c, po + y * nx + xm);
+            nb[1][c] = U(c, po + y * nx + xp);
+            nb[2][c] = U(c, po + ym * nx + x);
+            nb[3][c] = U(c, po + yp * nx + x);
+            nb[4][c] = zm[c];
+            nb[5][c] = zp[c];
+        }
+        const int64_t b = ((int64_t)bz * A.Py + by) * A.Px + bx;
+        if (bz != kbz) {              // face delays of this block: reloaded only at block changes
+            kbz = bz;
+            kc[0] = lx == 0 ? krow[6 * b + 0] : 0;
+            kc[1] = lx == A.Wx - 1 ? krow[6 * b + 1] : 0;
+            kc[2] = ly == 0 ? krow[6 * b + 2] : 0;
+            kc[3] = ly == A.Wy - 1 ? krow[6 * b + 3] : 0;
+            kc[4] = krow[6 * b + 4];
+            kc[5] = krow[6 * b + 5];
+        }
+        const int kf[6] = {kc[0], kc[1], kc[2], kc[3], lz == 0 ? kc[4] : 0,
+                           lz == A.Wz - 1 ? kc[5] : 0};
+        const int px = lz * A.Wy + ly, py = lz * A.Wx + lx, pz = ly * A.Wx + lx;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int kk = kf[f];
+            if (kk > 0) {
+                const int a = f >> 1, sd = f & 1;
+                int n0 = bx, n1 = by, n2 = bz;
+                if (a == 0) n0 = wrap32(bx + (sd ? 1 : -1), A.Px);
+                else if (a == 1) n1 = wrap32(by + (sd ? 1 : -1), A.Py);
+                else n2 = wrap32(bz + (sd ? 1 : -1), A.Pz);
+                const int pos = a == 0 ? px : (a == 1 ? py : pz);
+                const int64_t off = (((int64_t)n2 * A.Py + n1) * A.Px + n0) * A.bstride +
+                                    A.foff[2 * a + (1 - sd)] + pos;
+                int s0 = A.slot0 - kk, s1 = A.slot0 - kk - 1;
+                if (s0 < 0) s0 += A.R;
+                if (s1 < 0) s1 += A.R;
+                const double *r0 = A.ring + s0 * A.level + off;
+                const double *r1 = A.ring + s1 * A.level + off;
+                const double dk = (double)kk;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double v0 = r0[c * A.psz[a]];
+                    nb[f][c] = A.stale ? v0 : v0 + dk * (v0 - r1[c * A.psz[a]]);
+                }
+            }
+        }
+        const double ux = zc[0], uy = zc[1], uz = zc[2];
+        double *out = A.uout + (int64_t)po + col;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double u = zc[c];
+            const double xl = nb[0][c], xr = nb[1][c], yl = nb[2][c], yh = nb[3][c];
+            const double zl = nb[4][c], zh = nb[5][c];
+            const double D1x = (xr - xl) * A.c1[0], D2x = ((xr - 2.0 * u) + xl) * A.c2[0];
+            const double D1y = (yh - yl) * A.c1[1], D2y = ((yh - 2.0 * u) + yl) * A.c2[1];
+            const double D1z = (zh - zl) * A.c1[2], D2z = ((zh - 2.0 * u) + zl) * A.c2[2];
+            const double lap = (D2x + D2y) + D2z;
+            const double adv = (ux * D1x + uy * D1y) + uz * D1z;
+            out[c * A.npt] = u + A.dt * (A.nu * lap - adv);
+        }
+        if (A.publish && (lx == 0 || lx == A.Wx - 1 || ly == 0 || ly == A.Wy - 1 || lz == 0 ||
+                          lz == A.Wz - 1)) {
+            double *base = A.ring + slot * A.level + b * A.bstride;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double u = zc[c];
+                if (lx == 0) base[A.foff[0] + c * A.psz[0] + px] = u;
+                if (lx == A.Wx - 1) base[A.foff[1] + c * A.psz[0] + px] = u;
+                if (ly == 0) base[A.foff[2] + c * A.psz[1] + py] = u;
+                if (ly == A.Wy - 1) base[A.foff[3] + c * A.psz[1] + py] = u;
+                if (lz == 0) base[A.foff[4] + c * A.psz[2] + pz] = u;
+                if (lz == A.Wz - 1) base[A.foff[5] + c * A.psz[2] + pz] = u;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { zm[c] = zc[c]; zc[c] = zp[c]; zp[c] = zq[c]; }
+    }
+}
+
 int zchunk(int64_t nz, int64_t tiles_xy)
 {
     // enough workgroups to fill 256 CUs several times over, long z runs otherwise
@@ -278,8 +618,20 @@ int at3_max_fuse(const at_ctx *) { return 1; }
 
 // kernel variants the autotuner may choose from (tile rows, prefetch depth,
 // register budget); every variant performs the same operations
-int at3_variants() { return 6; }
-static int k3_rows(int var) { static const int r[6] = {8, 8, 4, 4, 16, 16}; return r[var < 0 || var > 5 ? 0 : var]; }
+int at3_variants() { return 15; }
+static int k3_rows(int var)
+{
+    static const int r[15] = {8, 8, 4, 4, 16, 16, 8, 16, 4, 4, 8, 16, 8, 8, 16};
+    return r[var < 0 || var > 14 ? 0 : var];
+}
+// variants 6..8 need block widths that are multiples of the tile
+bool at3_variant_ok(const at_config *c, int var)
+{
+    if (var < 0 || var > 14) return false;
+    if (var < 6 || (var > 8 && var < 12)) return true;
+    const int64_t Wx = c->n[0] / c->p[0], Wy = c->n[1] / c->p[1];
+    return Wx % TX == 0 && Wy % k3_rows(var) == 0;
+}
 
 at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, int s, int publish)
 {
@@ -327,7 +679,16 @@ at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, i
     case 2: hipLaunchKernelGGL((k_step3d<4, 2, 4>), grid, block, 0, st, A); break;
     case 3: hipLaunchKernelGGL((k_step3d<4, 2, 3>), grid, block, 0, st, A); break;
     case 4: hipLaunchKernelGGL((k_step3d<16, 1, 2>), grid, block, 0, st, A); break;
-    default: hipLaunchKernelGGL((k_step3d<16, 2, 2>), grid, block, 0, st, A); break;
+    case 5: hipLaunchKernelGGL((k_step3d<16, 2, 2>), grid, block, 0, st, A); break;
+    case 6: hipLaunchKernelGGL((k_step3d_aligned<8, 4, 1>), grid, block, 0, st, A); break;
+    case 7: hipLaunchKernelGGL((k_step3d_aligned<16, 2, 1>), grid, block, 0, st, A); break;
+    case 8: hipLaunchKernelGGL((k_step3d_aligned<4, 6, 1>), grid, block, 0, st, A); break;
+    case 12: hipLaunchKernelGGL((k_step3d_aligned<8, 2, 2>), grid, block, 0, st, A); break;
+    case 13: hipLaunchKernelGGL((k_step3d_aligned<8, 2, 4>), grid, block, 0, st, A); break;
+    case 14: hipLaunchKernelGGL((k_step3d_aligned<16, 1, 4>), grid, block, 0, st, A); break;
+    case 9: hipLaunchKernelGGL((k_step3d_direct<4>), grid, block, 0, st, A); break;
+    case 10: hipLaunchKernelGGL((k_step3d_direct<8>), grid, block, 0, st, A); break;
+    default: hipLaunchKernelGGL((k_step3d_direct<16>), grid, block, 0, st, A); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return at_fail(AT_ERR_HIP, hipGetErrorString(e));
