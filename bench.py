@@ -24,7 +24,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0          # MI355X HBM3E
-FP64_ADDMUL_PEAK_TFLOPS = 39.3  # 256 CU x 64 FP64 lanes/clk x 2.4 GHz, one op per add or mul
+FP64_ADDMUL_PEAK_TFLOPS = 39.3  # 256 CU x 64 FP64 lanes/clk x 2.4 GHz: one FP64 VALU
+                                # instruction per lane per clock (78.6 with every one an FMA)
 METRIC = "grid-point updates/s & % HBM peak (AT step, adjoint, batched) vs plain form"
 
 
@@ -32,9 +33,14 @@ def eprint(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def flops_per_update(order):
-    # stencil + update without contraction: order 2: 11, order 4: 17
-    return 11 if order == 2 else 17
+def flops_per_update(order, arith=0):
+    """(FP64 flops, FP64 VALU instructions) of one interior update.  Exact
+    order, no contraction: every operation is one instruction (order 2: 11,
+    order 4: 17).  Contracted mode (an FMA is two flops in one instruction):
+    order 2: 9 flops in 6 instructions, order 4: 15 flops in 10."""
+    if arith == 0:
+        return (11, 11) if order == 2 else (17, 17)
+    return (9, 6) if order == 2 else (15, 10)
 
 
 def algo_bytes_1d(N, P, order, L, dist, s):
@@ -70,11 +76,11 @@ class Timer:
         return sum(a.elapsed_time(b) for a, b in self.pairs)
 
 
-def bench_c2(args, torch, at, I, fuse=None, label="main"):
+def bench_c2(args, torch, at, I, fuse=None, label="main", arith=0):
     wl = I.wl_powerlaw_1d()
     N, P = wl.n[0], wl.p[0]
     st = at.Stepper(n=N, p=P, order=wl.order, L=wl.L, nu=wl.nu, dt=wl.dt, nsteps_max=wl.nsteps,
-                    seed=wl.seed, dist=wl.dist)
+                    seed=wl.seed, dist=wl.dist, arith=arith)
     u0 = torch.from_numpy(wl.u0).cuda()
     if fuse is None:
         s = st.autotune(u0, 100)
@@ -103,12 +109,16 @@ def bench_c2(args, torch, at, I, fuse=None, label="main"):
     # the last launch of a run may carry fewer steps; use the mean steps per launch
     s_mean = wl.nsteps / launches
     bytes_launch = algo_bytes_1d(N, P, wl.order, wl.L, wl.dist, s_mean)
-    flops_launch = flops_per_update(wl.order) * N * s_mean
+    fl, ins = flops_per_update(wl.order, arith)
+    flops_launch = fl * N * s_mean
     gbps = bytes_launch / (ms_launch * 1e-3) / 1e9
     tflops = flops_launch / (ms_launch * 1e-3) / 1e12
+    # issue-rate ceiling for this instruction mix: 39.3 T FP64 instructions/s
+    alu_peak = FP64_ADDMUL_PEAK_TFLOPS * fl / ins
     res = dict(wl=wl, s=s, wall=wall, ms_per_step=wall * 1e3 / args.steps,
                value=N * wl.nsteps * args.steps / wall, ms_launch=ms_launch, gbps=gbps,
-               tflops=tflops, launches=launches, bytes_launch=bytes_launch, u0=wl.u0,
+               tflops=tflops, alu_peak=alu_peak, arith=arith, launches=launches,
+               bytes_launch=bytes_launch, u0=wl.u0,
                delays=st.delays(), uT=u)
     eprint("[%s] fuse %d: %.3f ms/run, %.4g updates/s, kernel %.1f us/launch, %.0f GB/s, "
            "%.2f TFLOP/s" % (label, s, res["ms_per_step"], res["value"], ms_launch * 1e3, gbps,
@@ -119,9 +129,8 @@ def bench_c2(args, torch, at, I, fuse=None, label="main"):
 def roofline(r):
     hbm = dict(bound="hbm", achieved=round(r["gbps"], 2), peak=HBM_PEAK_GBPS, unit="GB/s",
                frac=round(r["gbps"] / HBM_PEAK_GBPS, 4), traffic=None)
-    alu = dict(bound="alu", achieved=round(r["tflops"], 4), peak=FP64_ADDMUL_PEAK_TFLOPS,
-               unit="TFLOP/s", frac=round(r["tflops"] / FP64_ADDMUL_PEAK_TFLOPS, 4),
-               traffic=None)
+    alu = dict(bound="alu", achieved=round(r["tflops"], 4), peak=round(r["alu_peak"], 2),
+               unit="TFLOP/s", frac=round(r["tflops"] / r["alu_peak"], 4), traffic=None)
     return (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
 
 
@@ -145,18 +154,28 @@ def cpu_baseline(res):
                        "order 4, same u0 and delays), %.1f s wall" % (steps, el))
 
 
+def copy_ceiling(torch, n=1 << 27, reps=5):
+    """Achieved rate of a plain device copy of n doubles (read + write), on
+    the same stream and with the same events as the kernels: the practical
+    HBM ceiling next to the 8 TB/s nameplate."""
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    tm = Timer(torch)
+    for _ in range(reps):
+        tm.start()
+        dst.copy_(src)
+        tm.stop()
+    ms = tm.total_ms() / reps
+    del src, dst
+    return ms, 16.0 * n / (ms * 1e-3) / 1e9
+
+
 def calibrate(torch):
     """Plain device copy of a known size: 2^27 doubles (1 GiB) read and written
     per launch, 5 launches, for scaling the HBM byte counters."""
     n = 1 << 27
-    src = torch.ones(n, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    tm = Timer(torch)
-    for _ in range(5):
-        tm.start()
-        dst.copy_(src)
-        tm.stop()
-    ms = tm.total_ms() / 5
+    ms, _ = copy_ceiling(torch, n)
     eprint("[calibrate] copy of %d bytes: %.3f ms, %.1f GB/s (read+write)" %
            (8 * n, ms, 16.0 * n / (ms * 1e-3) / 1e9))
     print(json.dumps({"calibration_bytes_read": 8 * n, "calibration_bytes_written": 8 * n,
@@ -169,7 +188,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--only", choices=["main", "all"], default="all")
-    ap.add_argument("--legs", default="plain,batched,adjoint,3d",
+    ap.add_argument("--legs", default="plain,contracted,batched,adjoint,3d",
                     help="comma-separated sub-measurements run with --only all")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fuse", type=int, default=None,
@@ -212,7 +231,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": main_res["wl"].name, "n": main_res["wl"].n[0],
                    "p": main_res["wl"].p[0], "order": 4, "L": 4, "nsteps": 2000,
-                   "fuse_steps": main_res["s"], "kernel": "k_step1d<4,false>"},
+                   "fuse_steps": main_res["s"], "arith": "exact order, no contraction",
+                   "kernel": "k_step1d_aligned<4,false,false>"},
         "roofline": rl,
         "roofline_other": rl_other,
     }
@@ -229,6 +249,20 @@ def main():
                              "fused_speedup": round(main_res["value"] / plain["value"], 3),
                              "bitwise_equal_to_fused": bool(torch.equal(plain["uT"],
                                                                         main_res["uT"]))}
+    if args.only == "all" and "contracted" in legs:
+        con = bench_c2(args, torch, at, I, label="contracted", arith=1)
+        crl, _ = roofline(con)
+        import numpy as np
+        a = main_res["uT"].cpu().numpy()
+        b = con["uT"].cpu().numpy()
+        paths["contracted_1d"] = {
+            "value": con["value"], "unit": "grid-point updates/s",
+            "ms_per_step": round(con["ms_per_step"], 4), "fuse_steps": con["s"],
+            "kernel_us_per_launch": round(con["ms_launch"] * 1e3, 3),
+            "roofline": crl,
+            "speedup_vs_exact_order": round(con["value"] / main_res["value"], 3),
+            "max_rel_diff_vs_exact_order_after_2000_steps":
+                float(np.max(np.abs(a - b)) / np.max(np.abs(a)))}
     if args.only == "all":
         for name, fn in EXTRA:
             if name not in legs:
@@ -238,6 +272,9 @@ def main():
             except Exception as e:   # reported, never hidden
                 paths[name] = {"error": "%s: %s" % (type(e).__name__, e)}
                 eprint("[%s] failed: %s" % (name, e))
+    ms_copy, copy_gbps = copy_ceiling(torch)
+    out["hbm_copy_gbps"] = round(copy_gbps, 1)
+    eprint("[copy] 1 GiB device copy: %.3f ms, %.0f GB/s" % (ms_copy, copy_gbps))
     if paths:
         out["paths"] = paths
     if not args.no_cpu:

@@ -98,7 +98,13 @@ typedef struct at_config {
     int32_t ckpt_every;       /* record mode: checkpoint interval C >= 1          */
     int32_t fuse_steps;       /* steps per launch s (1 = one launch per step);
                                  0 = let at_autotune choose (default 1 until then) */
-    int32_t reserved0;
+    int32_t arith;            /* 0: each formula evaluated in the fixed order
+                                 with separate roundings (bit-identical to a
+                                 reference evaluating the same order);
+                                 1 (1D only): fused multiply-adds with dt*c1 and
+                                 dt*nu*c2 folded, u' = u + A2*T2 - (a*A1)*T1 --
+                                 fewer instructions, same binary64 precision,
+                                 results differ in the last bits */
     void *stream;             /* hipStream_t for all work of this context         */
     void *workspace;          /* device memory owned by the caller                */
     uint64_t workspace_bytes;

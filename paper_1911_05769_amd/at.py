@@ -55,7 +55,7 @@ class Config(ctypes.Structure):
         ("record", ctypes.c_int32),
         ("ckpt_every", ctypes.c_int32),
         ("fuse_steps", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("arith", ctypes.c_int32),
         ("stream", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_uint64),
@@ -144,7 +144,7 @@ def levels_for_order(order: int) -> int:
 def make_config(*, dim=1, n, p, order=2, L=0, nu, dt, nsteps_max, length=2 * math.pi,
                 halo_mode=0, adv_mode=0, adv_speed=0.0, delays=None, seed=0,
                 dist=DIST_UNIFORM, record=False, ckpt_every=0, fuse_steps=1,
-                stream=None) -> Config:
+                stream=None, arith=0) -> Config:
     c = Config()
     c.abi_version = AT_ABI_VERSION
     c.dim = dim
@@ -164,6 +164,7 @@ def make_config(*, dim=1, n, p, order=2, L=0, nu, dt, nsteps_max, length=2 * mat
     c.record = 1 if record else 0
     c.ckpt_every = int(ckpt_every)
     c.fuse_steps = int(fuse_steps)
+    c.arith = int(arith)
     c.stream = stream
     c.workspace = None
     c.workspace_bytes = 0
@@ -194,14 +195,14 @@ class Stepper:
     def __init__(self, *, dim=1, n, p, order=2, L=0, nu, dt, nsteps_max,
                  length=2 * math.pi, halo_mode=0, adv_mode=0, adv_speed=0.0, delays=None,
                  seed=0, dist=DIST_UNIFORM, record=False, ckpt_every=0, fuse_steps=1,
-                 device="cuda"):
+                 device="cuda", arith=0):
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
         self.cfg = make_config(dim=dim, n=n, p=p, order=order, L=L, nu=nu, dt=dt,
                                nsteps_max=nsteps_max, length=length, halo_mode=halo_mode,
                                adv_mode=adv_mode, adv_speed=adv_speed, delays=delays,
                                seed=seed, dist=dist, record=record, ckpt_every=ckpt_every,
-                               fuse_steps=fuse_steps,
+                               fuse_steps=fuse_steps, arith=arith,
                                stream=ctypes.c_void_p(self.stream.cuda_stream))
         self.dim = dim
         self.shape = (int(self.cfg.n[0]),) if dim == 1 else \
@@ -340,10 +341,11 @@ class Batch:
         self._keep = []
 
     @classmethod
-    def from_workloads(cls, wls, device="cuda", fuse_steps=1):
+    def from_workloads(cls, wls, device="cuda", fuse_steps=1, arith=0):
         """Instances from inputs.Workload objects (1D)."""
         ins = [dict(n=w.n[0], p=w.p[0], order=w.order, L=w.L, nu=w.nu, dt=w.dt,
-                    nsteps_max=w.nsteps, seed=w.seed, dist=w.dist, length=w.length) for w in wls]
+                    nsteps_max=w.nsteps, seed=w.seed, dist=w.dist, length=w.length, arith=arith)
+               for w in wls]
         return cls(ins, device=device, fuse_steps=fuse_steps)
 
     def __del__(self):

@@ -53,6 +53,7 @@ struct Layout {
 
 struct Derived {
     int dim, order, h, m;
+    int L;          // delay bound
     int64_t N;      // total points
     int64_t F;      // faces
     int64_t nb;     // tiles / blocks
@@ -93,6 +94,8 @@ at_status derive(const at_config *c, Derived &d)
         return fail(AT_ERR_ARG, "delays_host is NULL");
     if (c->fuse_steps < 0 || c->fuse_steps > kMaxFuse)
         return fail(AT_ERR_ARG, "fuse_steps must be in 0..%d", kMaxFuse);
+    if (c->arith != 0 && c->arith != 1) return fail(AT_ERR_ARG, "arith must be 0 or 1");
+    if (c->arith == 1 && c->dim != 1) return fail(AT_ERR_ARG, "arith 1 is 1D only");
     if (c->record) {
         if (c->dim != 1) return fail(AT_ERR_ARG, "record mode (adjoint) is 1D only");
         if (c->ckpt_every < 1) return fail(AT_ERR_ARG, "record mode needs ckpt_every >= 1");
@@ -101,6 +104,7 @@ at_status derive(const at_config *c, Derived &d)
     d.order = c->order;
     d.h = c->order / 2;
     d.m = (c->order == 2) ? 2 : 3;
+    d.L = c->L;
     const int naxes = c->dim;
     d.N = 1;
     d.nb = 1;
@@ -215,7 +219,7 @@ int max_fuse_1d(const Derived &d)
     for (int s = 2; s <= kMaxFuse; ++s) {
         if (region_1d(d, s).CH < std::min<int64_t>(reg / 2, d.N)) break;
         const int NT = (int)((reg - 1) / d.W + 2);
-        if (step1d_lds_bytes(d.order, s, NT) > 64 * 1024) break;
+        if (step1d_lds_bytes(d.order, s, NT, d.L + d.m - 1) > 64 * 1024) break;
         best = s;
     }
     return best;
@@ -266,7 +270,7 @@ at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int 
     a.publish = publish;
     a.RL = (int32_t)rg.RL;
     a.slot0 = (int32_t)(n0 % a.R);
-    a.pad1 = 0;
+    a.D = c->cfg.L + d.m - 1;
     a.levels = levels;
     if (levels && !rg.aligned) return fail(AT_ERR_STATE, "level store needs the aligned layout");
     a.nu = c->cfg.nu;
@@ -274,8 +278,11 @@ at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int 
     a.c1 = d.c1[0];
     a.c2 = d.c2[0];
     a.cadv = c->cfg.adv_speed;
+    a.A1 = a.dt * a.c1;
+    a.A2 = a.dt * (a.nu * a.c2);
     const int64_t nblocks = (d.N + a.CH - 1) / a.CH;
-    AT_HIP(launch_step1d(a, d.order, c->cfg.adv_mode == 1, rg.aligned, nblocks, c->st));
+    AT_HIP(launch_step1d(a, d.order, c->cfg.adv_mode == 1, rg.aligned, c->cfg.arith == 1, nblocks,
+                         c->st));
     return AT_OK;
 }
 
@@ -662,7 +669,7 @@ at_status at_adjoint(at_ctx *c, const double *lambda_T, double *grad_u0, double 
 
 struct at_batch {
     int count = 0, order = 2;
-    bool linear = false;
+    bool linear = false, fma = false;
     hipStream_t st = nullptr;
     std::vector<at_config> cfg;
     std::vector<Derived> d;
@@ -744,16 +751,18 @@ at_status batch_tables(at_batch *b, int slot, int s, double *const *u, double *c
         a.publish = 1;
         a.RL = (int32_t)rg.RL;
         a.slot0 = 0;          // set per launch by the batched kernel
-        a.pad1 = 0;
+        a.D = b->cfg[j].L + d.m - 1;
         a.levels = nullptr;
         a.nu = b->cfg[j].nu;
         a.dt = b->cfg[j].dt;
         a.c1 = d.c1[0];
         a.c2 = d.c2[0];
         a.cadv = b->cfg[j].adv_speed;
+        a.A1 = a.dt * a.c1;
+        a.A2 = a.dt * (a.nu * a.c2);
         const int64_t nch = (d.N + rg.CH - 1) / rg.CH;
         for (int64_t c = 0; c < nch; ++c) T.push_back(make_int2(j, (int)c));
-        lds = std::max(lds, step1d_lds_bytes(b->order, s, a.NT));
+        lds = std::max(lds, step1d_lds_bytes(b->order, s, a.NT, a.D));
     }
     if ((int64_t)T.size() > b->tbl_cap) return fail(AT_ERR_STATE, "batch block table overflow");
     AT_HIP(hipStreamSynchronize(b->st));
@@ -779,7 +788,8 @@ at_status batch_launches(at_batch *b, int64_t n0, int64_t nsteps, double *const 
         const int s = (int)std::min<int64_t>(b->fuse, nsteps - done);
         const int slot = s == b->slot_s[0] ? 0 : 1;
         AT_HIP(launch_step1d_batch(b->desc_dev[slot], b->tbl_dev[slot], b->slot_blocks[slot],
-                                   b->order, b->linear, n0 + done, flip, b->slot_lds[slot], stream));
+                                   b->order, b->linear, b->fma, n0 + done, flip, b->slot_lds[slot],
+                                   stream));
         flip ^= 1;
         done += s;
     }
@@ -809,8 +819,9 @@ static at_status batch_layout(const at_config *cfgs, int32_t count, std::vector<
         if (st) return fail(st, "instance %d: %s", j, g_err.c_str());
         if (cfgs[j].dim != 1) return fail(AT_ERR_ARG, "instance %d: batched form is 1D", j);
         if (cfgs[j].record) return fail(AT_ERR_ARG, "instance %d: record mode not batched", j);
-        if (cfgs[j].order != cfgs[0].order || cfgs[j].adv_mode != cfgs[0].adv_mode)
-            return fail(AT_ERR_ARG, "instance %d: all instances share order and adv_mode", j);
+        if (cfgs[j].order != cfgs[0].order || cfgs[j].adv_mode != cfgs[0].adv_mode ||
+            cfgs[j].arith != cfgs[0].arith)
+            return fail(AT_ERR_ARG, "instance %d: all instances share order, adv_mode and arith", j);
         if (ds[j].W % step1d_points_per_thread() != 0)
             return fail(AT_ERR_SHAPE, "instance %d: tile width %lld is not a multiple of %d", j,
                         (long long)ds[j].W, step1d_points_per_thread());
@@ -889,6 +900,7 @@ at_status at_batch_init(const at_config *cfgs, int32_t count, void *workspace,
     b->count = count;
     b->order = cfgs[0].order;
     b->linear = cfgs[0].adv_mode == 1;
+    b->fma = cfgs[0].arith == 1;
     b->st = (hipStream_t)cfgs[0].stream;
     b->cfg.assign(cfgs, cfgs + count);
     b->d = ds;

@@ -27,9 +27,10 @@ struct Step1D {
     int32_t publish;          // 1: write level n edges to the ring
     int32_t RL;               // left rim of the loaded region (aligned kernel)
     int32_t slot0;            // n0 mod R (ring slot of level n0)
-    int32_t pad1;
+    int32_t D;                // delayed levels below n0 a step may read: L + m - 1
     double *levels;           // optional: levels n0+1 .. n0+s-1 stored at levels + t*N (aligned kernel)
     double nu, dt, c1, c2, cadv;
+    double A1, A2;            // contracted mode: dt*c1, dt*(nu*c2)
 };
 
 // Reverse (adjoint) step at level n of the 1D stepper.
@@ -85,13 +86,14 @@ hipError_t launch_delays(int8_t *out, int64_t nsteps, int64_t F, int L, int m, i
                          uint64_t seed, hipStream_t st);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
-size_t step1d_lds_bytes(int order, int s, int NT);
+size_t step1d_lds_bytes(int order, int s, int NT, int D);
 int step1d_points_per_thread();
 int step1d_plain_points_per_thread();
-hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned,
+hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, bool fma,
                          int64_t nblocks, hipStream_t st);
 hipError_t launch_step1d_batch(const Step1D *descs, const int2 *tbl, int64_t nblocks, int order,
-                               bool linear, int64_t n0, int flip, size_t lds, hipStream_t st);
+                               bool linear, bool fma, int64_t n0, int flip, size_t lds,
+                               hipStream_t st);
 hipError_t launch_adj1d(const Adj1D &a, int order, bool linear, int64_t nblocks,
                         hipStream_t st);
 int adj1d_points_per_block();

@@ -54,20 +54,39 @@ __device__ __forceinline__ int64_t ring_slot(const Step1D &a, int64_t d)
     return x;
 }
 
+template <bool FMA = false>
 __device__ __forceinline__ double extrap(int kk, bool stale, double v0, double v1, double v2,
                                          int M)
 {
     if (stale) return v0;
     const double dk = (double)kk;
     const double d1 = v0 - v1;
+    if constexpr (FMA) {
+        if (M == 2) return fma(dk, d1, v0);
+        const double w2 = 0.5 * dk * (dk + 1.0);
+        return fma(w2, d1 - (v1 - v2), fma(dk, d1, v0));
+    }
     if (M == 2) return v0 + dk * d1;
     const double w2 = 0.5 * dk * (dk + 1.0);
     return (v0 + dk * d1) + w2 * (d1 - (v1 - v2));
 }
 
-template <int ORDER, bool LINEAR>
+template <int ORDER, bool LINEAR, bool FMA = false>
 __device__ __forceinline__ double update(const double *nb, double u, const Step1D &a)
 {
+    if constexpr (FMA) {
+        // contracted: u' = u + A2*T2 - (a*A1)*T1 with T1 = D1/c1, T2 = D2/c2
+        double T1, T2;
+        if constexpr (ORDER == 2) {
+            T1 = nb[1] - nb[0];
+            T2 = fma(-2.0, u, nb[1]) + nb[0];
+        } else {
+            T1 = fma(8.0, nb[2] - nb[1], -(nb[3] - nb[0]));
+            T2 = fma(16.0, nb[2] + nb[1], fma(-30.0, u, -(nb[3] + nb[0])));
+        }
+        const double adv = LINEAR ? a.cadv : u;
+        return fma(a.A2, T2, fma(-(adv * a.A1), T1, u));
+    }
     double D1, D2;
     if constexpr (ORDER == 2) {
         const double l1 = nb[0], r1 = nb[1];
@@ -83,7 +102,7 @@ __device__ __forceinline__ double update(const double *nb, double u, const Step1
     return u + a.dt * F;
 }
 
-template <int ORDER, bool LINEAR>
+template <int ORDER, bool LINEAR, bool FMA>
 __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
 {
     constexpr int H = ORDER / 2;
@@ -92,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
     extern __shared__ double lds[];
     double *stage = lds;                                  // [kThreads*PPT + kThreads]
     double *xch = lds;                                    // [2][kThreads][2H]  (aliases stage)
-    double *eh = lds + 2 * kThreads * 2 * H;              // [s-1][NT][2][H]    (aliases stage)
+    double *eh = lds + 2 * kThreads * 2 * H;              // [D+s-1][NT][2][H]  (aliases stage)
 
     const int tid = threadIdx.x;
     const int64_t c0 = (int64_t)blockIdx.x * a.CH;
@@ -179,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
             double nb[2 * H];
 #pragma unroll
             for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
-            res[j] = update<ORDER, LINEAR>(nb, w[H + j], a);
+            res[j] = update<ORDER, LINEAR, FMA>(nb, w[H + j], a);
         }
         // ---- points next to a tile edge: stencil again with AT halo values
         if (has_edge) {
@@ -222,12 +241,12 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
                                             vv[jj] = a.ring[((ring_slot(a, lev - a.n0) * a.P + stp) * 2 + sside) * H + q];
                                     }
                                 }
-                                v = extrap(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
+                                v = extrap<FMA>(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
                             }
                         }
                         nb[sl] = v;
                     }
-                    res[j] = update<ORDER, LINEAR>(nb, w[H + j], a);
+                    res[j] = update<ORDER, LINEAR, FMA>(nb, w[H + j], a);
                 }
             }
         }
@@ -254,9 +273,13 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
 // part of its register window, a thread that ends a tile its right ones, and
 // then every point runs the same stencil (the split of section 5.2); the
 // window slots replaced belong to this thread alone.
-// FUSED = false: exactly one step per launch (every delayed level comes from
-// the ring; no LDS edge history)
-template <int ORDER, bool LINEAR, bool FUSED = true, int PPT = kPPT>
+// FUSED = true: before the first step the launch copies into LDS the delay
+// rows of its s steps for every tile of the region and the ring levels
+// n0-D .. n0-1 of those tiles' edges; with the edges of the levels it
+// computes recorded beside them, no step waits on a global load.
+// FUSED = false: exactly one step per launch (delays and delayed levels read
+// from global memory where used; no LDS edge history)
+template <int ORDER, bool LINEAR, bool FMA, bool FUSED = true, int PPT = kPPT>
 __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chunk)
 {
     constexpr int H = ORDER / 2;
@@ -264,7 +287,7 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     extern __shared__ double lds[];
     double *stage = lds;                                  // [kThreads*PPT + kThreads]
     double *xch = lds;                                    // [2][kThreads][2H]  (aliases stage)
-    double *eh = lds + 2 * kThreads * 2 * H;              // [s-1][NT][2][H]    (aliases stage)
+    double *eh = lds + 2 * kThreads * 2 * H;              // [D+s-1][NT][2][H]  (aliases stage)
 
     const int tid = threadIdx.x;
     const int64_t c0 = chunk * a.CH;
@@ -295,6 +318,37 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     for (int q = 0; q < H; ++q) { w[q] = 0.0; w[PPT + H + q] = 0.0; }
     __syncthreads();
 
+    // ---- LDS copies of this launch's delays and of the ring levels below n0
+    // (eh row d holds level n0 - D + d; kd[(t*NT + tl)*2 + side] the delay
+    // of region tile tl's face at level n0 + t)
+    const int D = a.D;
+    int8_t *kd = reinterpret_cast<int8_t *>(eh + (size_t)(D + S - 1) * a.NT * 2 * H);
+    if constexpr (FUSED) {
+        int64_t tb = floordiv(G0, a.W) % a.P;
+        if (tb < 0) tb += a.P;
+        const int64_t F2 = 2 * a.P;
+        const int nk = S * a.NT * 2;
+        for (int e = tid; e < nk; e += kThreads) {
+            const int side = e & 1;
+            const int tl = (e >> 1) % a.NT;
+            const int t = (e >> 1) / a.NT;
+            const int64_t tp = (tb + tl) % a.P;
+            kd[e] = a.delays[(a.n0 + t) * F2 + 2 * tp + side];
+        }
+        const int nr = D * a.NT * 2 * H;
+        for (int e = tid; e < nr; e += kThreads) {
+            const int q = e % H;
+            const int side = (e / H) & 1;
+            const int tl = (e / (2 * H)) % a.NT;
+            const int d = (e / (2 * H)) / a.NT;
+            const int64_t lev = a.n0 - D + d;
+            if (lev >= 0) {
+                const int64_t tp = (tb + tl) % a.P;
+                eh[e] = a.ring[((ring_slot(a, lev - a.n0) * a.P + tp) * 2 + side) * H + q];
+            }
+        }
+    }
+
     const int rp0 = tid * PPT;
     const int64_t Gt = G0 + rp0;
     const int64_t tdiv = floordiv(Gt, a.W);
@@ -320,11 +374,11 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
 #pragma unroll
             for (int q = 0; q < H; ++q) {
                 if (lo_edge) {
-                    if (FUSED && t < S - 1) eh[((t * a.NT + tl0) * 2 + 0) * H + q] = w[H + q];
+                    if (FUSED && t < S - 1) eh[(((t + D) * a.NT + tl0) * 2 + 0) * H + q] = w[H + q];
                     if (a.publish && owns) a.ring[((slot * a.P + tp0) * 2 + 0) * H + q] = w[H + q];
                 }
                 if (hi_edge) {
-                    if (FUSED && t < S - 1) eh[((t * a.NT + tl0) * 2 + 1) * H + q] = w[PPT + q];
+                    if (FUSED && t < S - 1) eh[(((t + D) * a.NT + tl0) * 2 + 1) * H + q] = w[PPT + q];
                     if (a.publish && owns) a.ring[((slot * a.P + tp0) * 2 + 1) * H + q] = w[PPT + q];
                 }
             }
@@ -344,9 +398,15 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
         }
         // ---- AT halo approximation at tile edges (k = 0: the raw neighbour stays)
         if (lo_edge || hi_edge) {
-            const int8_t *krow = a.delays + n * F;
-            const int kl = (lo_edge && tid > 0) ? krow[2 * tp0 + 0] : 0;   // tid 0: no left source
-            const int kr = hi_edge ? krow[2 * tp0 + 1] : 0;
+            int kl = 0, kr = 0;                                       // tid 0: no left source
+            if constexpr (FUSED) {
+                if (lo_edge && tid > 0) kl = kd[(t * a.NT + tl0) * 2 + 0];
+                if (hi_edge) kr = kd[(t * a.NT + tl0) * 2 + 1];
+            } else {
+                const int8_t *krow = a.delays + n * F;
+                if (lo_edge && tid > 0) kl = krow[2 * tp0 + 0];
+                if (hi_edge) kr = krow[2 * tp0 + 1];
+            }
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
                 const int kk = side == 0 ? kl : kr;
@@ -361,12 +421,12 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
                         for (int jj = 0; jj < M; ++jj) {
                             if (jj == 0 || !a.stale) {
                                 const int64_t lev = n - kk - jj;
-                                vv[jj] = (FUSED && lev >= a.n0)
-                                    ? eh[(((int)(lev - a.n0) * a.NT + stl) * 2 + sside) * H + q]
+                                vv[jj] = FUSED
+                                    ? eh[((((int)(lev - a.n0) + D) * a.NT + stl) * 2 + sside) * H + q]
                                     : a.ring[((ring_slot(a, lev - a.n0) * a.P + stp) * 2 + sside) * H + q];
                             }
                         }
-                        const double hv = extrap(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
+                        const double hv = extrap<FMA>(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
                         if (side == 0) w[q] = hv;
                         else w[PPT + H + q] = hv;
                     }
@@ -380,7 +440,7 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
             double nb[2 * H];
 #pragma unroll
             for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
-            res[j] = update<ORDER, LINEAR>(nb, w[H + j], a);
+            res[j] = update<ORDER, LINEAR, FMA>(nb, w[H + j], a);
         }
 #pragma unroll
         for (int j = 0; j < PPT; ++j) w[H + j] = res[j];
@@ -404,24 +464,24 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     }
 }
 
-template <int ORDER, bool LINEAR>
+template <int ORDER, bool LINEAR, bool FMA>
 __global__ __launch_bounds__(kThreads) void k_step1d_aligned(Step1D a)
 {
-    step1d_aligned_body<ORDER, LINEAR>(a, blockIdx.x);
+    step1d_aligned_body<ORDER, LINEAR, FMA>(a, blockIdx.x);
 }
 
 // one step per launch (the plain form): 8 points per thread, a smaller
 // workgroup footprint and more workgroups in flight
-template <int ORDER, bool LINEAR>
+template <int ORDER, bool LINEAR, bool FMA>
 __global__ __launch_bounds__(kThreads) void k_step1d_plain(Step1D a)
 {
-    step1d_aligned_body<ORDER, LINEAR, false, kPPTPlain>(a, blockIdx.x);
+    step1d_aligned_body<ORDER, LINEAR, FMA, false, kPPTPlain>(a, blockIdx.x);
 }
 
 // Batched form: workgroup b advances chunk tbl[b].y of instance tbl[b].x;
 // instance descriptors carry each instance's grid, ring, delays and
 // coefficients; flip = 1 swaps the field pointers (ping-pong launches).
-template <int ORDER, bool LINEAR>
+template <int ORDER, bool LINEAR, bool FMA>
 __global__ __launch_bounds__(kThreads) void k_step1d_aligned_batch(const Step1D *descs,
                                                                    const int2 *tbl, int64_t n0,
                                                                    int flip)
@@ -435,7 +495,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d_aligned_batch(const Step1D 
         a.uin = a.uout;
         a.uout = const_cast<double *>(t);
     }
-    step1d_aligned_body<ORDER, LINEAR>(a, e.y);
+    step1d_aligned_body<ORDER, LINEAR, FMA>(a, e.y);
 }
 
 // Delay array: SplitMix64 (Steele, Lea & Flood 2014) output for the state
@@ -583,65 +643,59 @@ int grid_for(int64_t n)
 int step1d_points_per_thread() { return kPPT; }
 int step1d_plain_points_per_thread() { return kPPTPlain; }
 
-size_t step1d_lds_bytes(int order, int s, int NT)
+size_t step1d_lds_bytes(int order, int s, int NT, int D)
 {
     const int H = order / 2;
     const size_t stage = (size_t)kThreads * kPPT + kThreads;
-    const size_t steps = (size_t)2 * kThreads * 2 * H + (size_t)(s > 1 ? s - 1 : 0) * NT * 2 * H;
+    // exchange buffers, edge history of D + s - 1 levels, delays (bytes)
+    const size_t steps = (size_t)2 * kThreads * 2 * H + (size_t)(D + s - 1) * NT * 2 * H +
+                         ((size_t)s * NT * 2 + 7) / 8;
     return 8 * (stage > steps ? stage : steps);
 }
 
-hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned,
+hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, bool fma,
                          int64_t nblocks, hipStream_t st)
 {
-    size_t lds = step1d_lds_bytes(order, a.s, a.NT);
+    size_t lds = step1d_lds_bytes(order, a.s, a.NT, a.D);
     if (aligned && a.s == 1) {
         const size_t stage = (size_t)kThreads * kPPTPlain + kThreads;
         const size_t xch = (size_t)2 * kThreads * order;
         lds = 8 * (stage > xch ? stage : xch);
     }
     dim3 grid((unsigned)nblocks), block(kThreads);
-    if (aligned && a.s == 1) {
-        if (order == 2) {
-            if (linear) hipLaunchKernelGGL((k_step1d_plain<2, true>), grid, block, lds, st, a);
-            else hipLaunchKernelGGL((k_step1d_plain<2, false>), grid, block, lds, st, a);
-        } else {
-            if (linear) hipLaunchKernelGGL((k_step1d_plain<4, true>), grid, block, lds, st, a);
-            else hipLaunchKernelGGL((k_step1d_plain<4, false>), grid, block, lds, st, a);
-        }
-        return hipGetLastError();
-    }
-    if (aligned) {
-        if (order == 2) {
-            if (linear) hipLaunchKernelGGL((k_step1d_aligned<2, true>), grid, block, lds, st, a);
-            else hipLaunchKernelGGL((k_step1d_aligned<2, false>), grid, block, lds, st, a);
-        } else {
-            if (linear) hipLaunchKernelGGL((k_step1d_aligned<4, true>), grid, block, lds, st, a);
-            else hipLaunchKernelGGL((k_step1d_aligned<4, false>), grid, block, lds, st, a);
-        }
-        return hipGetLastError();
-    }
-    if (order == 2) {
-        if (linear) hipLaunchKernelGGL((k_step1d<2, true>), grid, block, lds, st, a);
-        else hipLaunchKernelGGL((k_step1d<2, false>), grid, block, lds, st, a);
-    } else {
-        if (linear) hipLaunchKernelGGL((k_step1d<4, true>), grid, block, lds, st, a);
-        else hipLaunchKernelGGL((k_step1d<4, false>), grid, block, lds, st, a);
-    }
+#define AT_L(K, O, LI, F) hipLaunchKernelGGL((K<O, LI, F>), grid, block, lds, st, a)
+#define AT_DISPATCH(K)                                                                   \
+    do {                                                                                 \
+        if (order == 2) {                                                                \
+            if (linear) { if (fma) AT_L(K, 2, true, true); else AT_L(K, 2, true, false); } \
+            else { if (fma) AT_L(K, 2, false, true); else AT_L(K, 2, false, false); }       \
+        } else {                                                                         \
+            if (linear) { if (fma) AT_L(K, 4, true, true); else AT_L(K, 4, true, false); } \
+            else { if (fma) AT_L(K, 4, false, true); else AT_L(K, 4, false, false); }       \
+        }                                                                                \
+    } while (0)
+    if (aligned && a.s == 1) AT_DISPATCH(k_step1d_plain);
+    else if (aligned) AT_DISPATCH(k_step1d_aligned);
+    else AT_DISPATCH(k_step1d);
+#undef AT_DISPATCH
+#undef AT_L
     return hipGetLastError();
 }
 
 hipError_t launch_step1d_batch(const Step1D *descs, const int2 *tbl, int64_t nblocks, int order,
-                               bool linear, int64_t n0, int flip, size_t lds, hipStream_t st)
+                               bool linear, bool fma, int64_t n0, int flip, size_t lds,
+                               hipStream_t st)
 {
     dim3 grid((unsigned)nblocks), block(kThreads);
+#define AT_BATCH(O, LI, F) hipLaunchKernelGGL((k_step1d_aligned_batch<O, LI, F>), grid, block, lds, st, descs, tbl, n0, flip)
     if (order == 2) {
-        if (linear) hipLaunchKernelGGL((k_step1d_aligned_batch<2, true>), grid, block, lds, st, descs, tbl, n0, flip);
-        else hipLaunchKernelGGL((k_step1d_aligned_batch<2, false>), grid, block, lds, st, descs, tbl, n0, flip);
+        if (linear) { if (fma) AT_BATCH(2, true, true); else AT_BATCH(2, true, false); }
+        else { if (fma) AT_BATCH(2, false, true); else AT_BATCH(2, false, false); }
     } else {
-        if (linear) hipLaunchKernelGGL((k_step1d_aligned_batch<4, true>), grid, block, lds, st, descs, tbl, n0, flip);
-        else hipLaunchKernelGGL((k_step1d_aligned_batch<4, false>), grid, block, lds, st, descs, tbl, n0, flip);
+        if (linear) { if (fma) AT_BATCH(4, true, true); else AT_BATCH(4, true, false); }
+        else { if (fma) AT_BATCH(4, false, true); else AT_BATCH(4, false, false); }
     }
+#undef AT_BATCH
     return hipGetLastError();
 }
 

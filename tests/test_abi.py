@@ -55,6 +55,8 @@ def _ws(**kw):
     (dict(record=True, ckpt_every=0), at.AT_ERR_ARG),
     (dict(dim=3, n=(16, 16, 16), p=(2, 2, 2), order=4), at.AT_ERR_ARG),
     (dict(adv_mode=2), at.AT_ERR_ARG),
+    (dict(arith=2), at.AT_ERR_ARG),
+    (dict(dim=3, n=(16, 16, 16), p=(2, 2, 2), order=2, arith=1), at.AT_ERR_ARG),
 ])
 def test_invalid_configs_rejected(kw, status):
     with pytest.raises(at.AtError) as e:
