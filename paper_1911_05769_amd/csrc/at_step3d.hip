@@ -60,6 +60,7 @@ struct Step3D {
 namespace {
 
 constexpr int TX = 64;        // tile width in x (one wave64 per row)
+constexpr int kZB = 64;       // z-blocks one chunk of the aligned kernel may span
 
 __device__ __forceinline__ int wrap32(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -247,17 +248,57 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
 }
 
 
+// One neighbour value triple (3 components) for a tile rim or a z face: the
+// ring levels n-k and n-k-1 of the neighbour block's face when k > 0, else
+// the raw field value (loaded twice from the same address).  Every lane of a
+// role issues the same six loads whatever k is, so the wait counts stay
+// static and no later wait drains the planes in flight.
+struct Nb3 {
+    double a0, a1, a2;        // level n-k (or the field)
+    double b0, b1, b2;        // level n-k-1 (or a repeat of a)
+    int k;
+};
+
+__device__ __forceinline__ Nb3 load_nb3(const double *ring, const double *field, int k, bool stale,
+                                        int64_t oring0, int64_t oring1, int64_t cring,
+                                        int64_t ofield, int64_t cfield)
+{
+    const double *p0 = k > 0 ? ring + oring0 : field + ofield;
+    const double *p1 = (k > 0 && !stale) ? ring + oring1 : p0;
+    const int64_t cs = k > 0 ? cring : cfield;
+    Nb3 r;
+    r.k = k;
+    r.a0 = p0[0];
+    r.a1 = p0[cs];
+    r.a2 = p0[2 * cs];
+    r.b0 = p1[0];
+    r.b1 = p1[cs];
+    r.b2 = p1[2 * cs];
+    return r;
+}
+
+// AT value H = v0 + k (v0 - v1) (Eq. (1), m = 2); the raw value when k = 0
+// and the level n-k value itself in the stale-halo mode
+__device__ __forceinline__ double at_h(int k, bool stale, double v0, double v1)
+{
+    return (k > 0 && !stale) ? v0 + (double)k * (v0 - v1) : v0;
+}
+
 // Aligned variant: block widths are multiples of the tile (Wx % 64 == 0,
 // Wy % TY == 0), so block faces can only lie on the tile's rims (x, y) or on
 // whole planes (z).  Wave 0 computes the x-rim halo values of the next plane
 // (lanes 0..2TY-1), waves 0 and 1 the y-rim rows, and every thread the z
 // neighbour of the next plane, all one plane ahead; the AT value replaces the
 // raw neighbour in the LDS rim (or the z register) and every point then runs
-// the same branch-free stencil (the split of section 5.2).
+// the same branch-free stencil (the split of section 5.2).  The face delays
+// of the chunk are copied to LDS first, and every load inside the march is
+// consumed one plane after it is issued.
 template <int TY, int MINW, int PF>
 __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
 {
+    static_assert(PF == 1 || PF == 2, "plane queue of 2 or 3 slots");
     __shared__ double pl[2][3][TY + 2][TX + 2];
+    __shared__ int8_t kdl[6 * kZB];
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int nx = (int)A.nx, ny = (int)A.ny, nz = (int)A.nz;
     const int X0 = blockIdx.x * TX, Y0 = blockIdx.y * TY;
@@ -272,190 +313,214 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
     const bool fxl = X0 % Wx == 0, fxh = (X0 + TX) % Wx == 0;    // tile edges on block faces
     const bool fyl = Y0 % Wy == 0, fyh = (Y0 + TY) % Wy == 0;
     const double *const U0 = A.uin;
-    auto U = [&](int c, int off) -> double { return U0[(int64_t)c * A.npt + off]; };
-    const int8_t *krow = A.delays + A.n * A.F;
-    int sl0 = A.slot0;
-    auto lvl = [&](int back) -> int64_t { int q = sl0 - back; if (q < 0) q += A.R; return (int64_t)q * A.level; };
-    auto blk = [&](int bxx, int byy, int bzz) -> int64_t {
-        return ((int64_t)bzz * A.Py + byy) * A.Px + bxx;
-    };
+    const int64_t npt = A.npt;
+    const bool stale = A.stale != 0;
+    const int sl0 = A.slot0;
+    const int64_t Py = A.Py, Px = A.Px, bstride = A.bstride, level = A.level;
+    const int R = A.R;
+
+    // face delays of the z-blocks of this chunk
+    const int bz0 = Z0 / Wz;
+    {
+        const int nzb = (Z1 - 1) / Wz - bz0 + 1;          // <= kZB (host bounds ZC)
+        const int t = ty * TX + tx;
+        const int8_t *krow = A.delays + A.n * A.F;
+        if (t < 6 * nzb) {
+            const int64_t b = ((int64_t)(bz0 + t / 6) * Py + by) * Px + bx;
+            kdl[t] = krow[6 * b + t % 6];
+        }
+    }
+
     // roles
     const bool xr_role = ty == 0 && tx < 2 * TY;
     const int xr_row = tx >> 1, xr_side = tx & 1;
     const int xr_x = xr_side ? wrap32(X0 + TX, nx) : wrap32(X0 - 1, nx);
     const int xr_ly = (Y0 + xr_row) - by * Wy;
     const bool xr_face = xr_side ? fxh : fxl;
+    const int xr_col = xr_side ? TX + 1 : 0;
+    const int64_t xr_blk = ((int64_t)wrap32(bx + (xr_side ? 1 : -1), A.Px)) +
+                           (int64_t)by * Px;                       // + bz * Py * Px
+    const int64_t xr_foff = xr_side ? A.foff[0] : A.foff[1];
     const bool yr_role = ty < 2;
     const int yr_y = ty ? wrap32(Y0 + TY, ny) : wrap32(Y0 - 1, ny);
     const bool yr_face = ty ? fyh : fyl;
     const int yr_row = ty ? TY + 1 : 0;
-    const int xr_col = xr_side ? TX + 1 : 0;
-    const int nbx = wrap32(bx + (xr_side ? 1 : -1), A.Px);
-    const int nby = wrap32(by + (ty ? 1 : -1), A.Py);
+    const int64_t yr_blk = (int64_t)bx + (int64_t)wrap32(by + (ty ? 1 : -1), A.Py) * Px;
+    const int64_t yr_foff = ty ? A.foff[2] : A.foff[3];
+    const int64_t z_blk = (int64_t)bx + (int64_t)by * Px;
+    const int64_t zlo_foff = A.foff[5], zhi_foff = A.foff[4];
+    const int64_t psz0 = A.psz[0], psz1 = A.psz[1], psz2 = A.psz[2];
+    const int64_t PyPx = Py * Px;
+    auto lvl = [=](int back) -> int64_t {
+        int q = sl0 - back;
+        if (q < 0) q += R;
+        return (int64_t)q * level;
+    };
 
-    // loads of one plane's rims and z neighbour ("issue"), finished later
-    double xv0[3], xv1[3], yv0[3], yv1[3], zv0[3], zv1[3];
-    int xk = 0, yk = 0, zk = 0, zside = 0;
-    int kbz = -1, kc[6] = {0, 0, 0, 0, 0, 0};   // face delays of the current z-block
+    // planes z-1 and z in registers; planes z+1 .. z+PF in a queue of PF+1
+    // register slots that rotates by renaming (the loop is unrolled PF+1
+    // times): a slot whose load is still in flight is never copied
+    double zm0, zm1, zm2, zc0, zc1, zc2;
+    double qa[3], qb[3], qc[3];
+    zm0 = U0[wrap32(Z0 - 1, nz) * plane + col];
+    zm1 = U0[npt + wrap32(Z0 - 1, nz) * plane + col];
+    zm2 = U0[2 * npt + wrap32(Z0 - 1, nz) * plane + col];
+    zc0 = U0[Z0 * plane + col];
+    zc1 = U0[npt + Z0 * plane + col];
+    zc2 = U0[2 * npt + Z0 * plane + col];
+    {
+        const int o = wrap32(Z0 + 1, nz) * plane + col;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) qa[c] = U0[c * npt + o];
+    }
+    if (PF == 2) {
+        const int o = wrap32(Z0 + 2, nz) * plane + col;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) qb[c] = U0[c * npt + o];
+    }
+    __syncthreads();                                      // kdl ready
+
+    // loads of plane p's rims and z neighbour, consumed one plane later
+    Nb3 xr{}, yr{}, zr{};
+    int zside = 0;
     auto issue = [&](int p) {
         const int bz = p / Wz, lz = p - bz * Wz;
-        const int64_t b = blk(bx, by, bz);
-        if (bz != kbz) {
-            kbz = bz;
-#pragma unroll
-            for (int f = 0; f < 6; ++f) kc[f] = krow[6 * b + f];
-        }
+        const int8_t *kc = kdl + 6 * (bz - bz0);
+        const int64_t zoff = (int64_t)bz * PyPx;
         if (xr_role) {
-            xk = xr_face ? kc[xr_side] : 0;
-            if (xk > 0) {
-                const int64_t off = blk(nbx, by, bz) * A.bstride + A.foff[1 - xr_side] +
-                                    lz * Wy + xr_ly;
-                const int64_t o0 = lvl(xk) + off, o1 = lvl(xk + 1) + off;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    xv0[c] = A.ring[o0 + c * A.psz[0]];
-                    xv1[c] = A.stale ? 0.0 : A.ring[o1 + c * A.psz[0]];
-                }
-            } else {
-                const int o = p * plane + (Y0 + xr_row) * nx + xr_x;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) xv0[c] = U(c, o);
-            }
+            const int k = xr_face ? kc[xr_side] : 0;
+            const int64_t off = (xr_blk + zoff) * bstride + xr_foff + lz * Wy + xr_ly;
+            xr = load_nb3(A.ring, U0, k, stale, lvl(k) + off, lvl(k + 1) + off, psz0,
+                          (int64_t)p * plane + (Y0 + xr_row) * nx + xr_x, npt);
         }
         if (yr_role) {
-            yk = yr_face ? kc[2 + ty] : 0;
-            if (yk > 0) {
-                const int64_t off = blk(bx, nby, bz) * A.bstride + A.foff[2 + (1 - ty)] +
-                                    lz * Wx + lx;
-                const int64_t o0 = lvl(yk) + off, o1 = lvl(yk + 1) + off;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    yv0[c] = A.ring[o0 + c * A.psz[1]];
-                    yv1[c] = A.stale ? 0.0 : A.ring[o1 + c * A.psz[1]];
-                }
-            } else {
-                const int o = p * plane + yr_y * nx + x;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) yv0[c] = U(c, o);
-            }
+            const int k = yr_face ? kc[2 + ty] : 0;
+            const int64_t off = (yr_blk + zoff) * bstride + yr_foff + lz * Wx + lx;
+            yr = load_nb3(A.ring, U0, k, stale, lvl(k) + off, lvl(k + 1) + off, psz1,
+                          (int64_t)p * plane + yr_y * nx + x, npt);
         }
-        // z neighbour across a block face of plane p
-        zk = 0;
         zside = lz == 0 ? 0 : 1;
-        if (lz == 0 || lz == Wz - 1) zk = kc[4 + zside];
-        if (zk > 0) {
+        const int k = (lz == 0 || lz == Wz - 1) ? kc[4 + zside] : 0;   // uniform over the tile
+        zr.k = k;
+        if (k > 0) {
             const int nbz = wrap32(bz + (zside ? 1 : -1), A.Pz);
-            const int64_t off = blk(bx, by, nbz) * A.bstride + A.foff[4 + (1 - zside)] +
-                                ly * Wx + lx;
-            const int64_t o0 = lvl(zk) + off, o1 = lvl(zk + 1) + off;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                zv0[c] = A.ring[o0 + c * A.psz[2]];
-                zv1[c] = A.stale ? 0.0 : A.ring[o1 + c * A.psz[2]];
-            }
+            const int64_t off = (z_blk + (int64_t)nbz * PyPx) * bstride +
+                                (zside ? zhi_foff : zlo_foff) + ly * Wx + lx;
+            zr = load_nb3(A.ring, U0, k, stale, lvl(k) + off, lvl(k + 1) + off, psz2, 0, npt);
         }
     };
-    auto ext = [&](int kk, double v0, double v1) -> double {
-        return A.stale ? v0 : v0 + (double)kk * (v0 - v1);
-    };
-    // finish plane p's rims into LDS buffer bf
+    // plane p's rims into LDS buffer bf
     auto finish_rims = [&](int bf) {
-        if (xr_role)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                pl[bf][c][xr_row + 1][xr_col] = xk > 0 ? ext(xk, xv0[c], xv1[c]) : xv0[c];
-        if (yr_role)
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                pl[bf][c][yr_row][tx + 1] = yk > 0 ? ext(yk, yv0[c], yv1[c]) : yv0[c];
+        if (xr_role) {
+            pl[bf][0][xr_row + 1][xr_col] = at_h(xr.k, stale, xr.a0, xr.b0);
+            pl[bf][1][xr_row + 1][xr_col] = at_h(xr.k, stale, xr.a1, xr.b1);
+            pl[bf][2][xr_row + 1][xr_col] = at_h(xr.k, stale, xr.a2, xr.b2);
+        }
+        if (yr_role) {
+            pl[bf][0][yr_row][tx + 1] = at_h(yr.k, stale, yr.a0, yr.b0);
+            pl[bf][1][yr_row][tx + 1] = at_h(yr.k, stale, yr.a1, yr.b1);
+            pl[bf][2][yr_row][tx + 1] = at_h(yr.k, stale, yr.a2, yr.b2);
+        }
     };
 
-    // register queue: zq[0] = plane z+1, ..., zq[PF] = plane z+1+PF (in flight)
-    double zm[3], zc[3], zq[PF + 1][3], hz[3];
+    double hz0 = 0.0, hz1 = 0.0, hz2 = 0.0;
     bool hz_lo = false, hz_hi = false;      // plane's z neighbour replaced by hz (low / high)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        zm[c] = U(c, wrap32(Z0 - 1, nz) * plane + col);
-        zc[c] = U(c, Z0 * plane + col);
-#pragma unroll
-        for (int q = 0; q < PF; ++q)
-            zq[q][c] = (q == 0 || Z0 + q < Z1) ? U(c, wrap32(Z0 + 1 + q, nz) * plane + col) : 0.0;
-    }
+    auto take_z = [&]() {
+        hz_lo = hz_hi = false;
+        if (zr.k > 0) {
+            hz0 = at_h(zr.k, stale, zr.a0, zr.b0);
+            hz1 = at_h(zr.k, stale, zr.a1, zr.b1);
+            hz2 = at_h(zr.k, stale, zr.a2, zr.b2);
+            hz_lo = zside == 0;
+            hz_hi = zside == 1;
+        }
+    };
     issue(Z0);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) pl[0][c][ty + 1][tx + 1] = zc[c];
+    pl[0][0][ty + 1][tx + 1] = zc0;
+    pl[0][1][ty + 1][tx + 1] = zc1;
+    pl[0][2][ty + 1][tx + 1] = zc2;
     finish_rims(0);
-    if (zk > 0) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) hz[c] = ext(zk, zv0[c], zv1[c]);
-        hz_lo = zside == 0;
-        hz_hi = zside == 1;
-    }
+    take_z();
     if (Z0 + 1 < Z1) issue(Z0 + 1);
     const int64_t slot = A.slot0;
+    const double c10 = A.c1[0], c11 = A.c1[1], c12 = A.c1[2];
+    const double c20 = A.c2[0], c21 = A.c2[1], c22 = A.c2[2];
+    const double nu = A.nu, dt = A.dt;
 
     int bz = Z0 / Wz, lz = Z0 - bz * Wz;
-    for (int z = Z0; z < Z1; ++z, ++lz) {
+    // one plane: znx holds plane z+1 (complete), zld receives plane z+1+PF
+    auto body = [&](int z, double (&znx)[3], double (&zld)[3]) {
         if (lz == Wz) { lz = 0; ++bz; }
         const int buf = (z - Z0) & 1;
         const bool more = z + 1 < Z1;
+        {
+            const int o = wrap32(z + 1 + PF, nz) * plane + col;   // past Z1: unused, in bounds
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            zq[PF][c] = z + PF < Z1 ? U(c, wrap32(z + 1 + PF, nz) * plane + col) : 0.0;
+            for (int c = 0; c < 3; ++c) zld[c] = U0[c * npt + o];
+        }
         __syncthreads();
-        const double ux = zc[0], uy = zc[1], uz = zc[2];
+        const double ux = zc0, uy = zc1, uz = zc2;
         double *out = A.uout + (int64_t)z * plane + col;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double u = zc[c];
-            const double xl = pl[buf][c][ty + 1][tx], xr = pl[buf][c][ty + 1][tx + 2];
+            const double u = c == 0 ? zc0 : (c == 1 ? zc1 : zc2);
+            const double zmc = c == 0 ? zm0 : (c == 1 ? zm1 : zm2);
+            const double hzc = c == 0 ? hz0 : (c == 1 ? hz1 : hz2);
+            const double xl = pl[buf][c][ty + 1][tx], xh = pl[buf][c][ty + 1][tx + 2];
             const double yl = pl[buf][c][ty][tx + 1], yh = pl[buf][c][ty + 2][tx + 1];
-            const double zl = hz_lo ? hz[c] : zm[c];
-            const double zh = hz_hi ? hz[c] : zq[0][c];
-            const double D1x = (xr - xl) * A.c1[0], D2x = ((xr - 2.0 * u) + xl) * A.c2[0];
-            const double D1y = (yh - yl) * A.c1[1], D2y = ((yh - 2.0 * u) + yl) * A.c2[1];
-            const double D1z = (zh - zl) * A.c1[2], D2z = ((zh - 2.0 * u) + zl) * A.c2[2];
+            const double zl = hz_lo ? hzc : zmc;
+            const double zh = hz_hi ? hzc : znx[c];
+            const double D1x = (xh - xl) * c10, D2x = ((xh - 2.0 * u) + xl) * c20;
+            const double D1y = (yh - yl) * c11, D2y = ((yh - 2.0 * u) + yl) * c21;
+            const double D1z = (zh - zl) * c12, D2z = ((zh - 2.0 * u) + zl) * c22;
             const double lap = (D2x + D2y) + D2z;
             const double adv = (ux * D1x + uy * D1y) + uz * D1z;
-            out[c * A.npt] = u + A.dt * (A.nu * lap - adv);
+            out[c * npt] = u + dt * (nu * lap - adv);
         }
         // publish level-n values of points on block faces
         if (A.publish && (lx == 0 || lx == Wx - 1 || ly == 0 || ly == Wy - 1 || lz == 0 ||
                           lz == Wz - 1)) {
-            double *base = A.ring + slot * A.level + blk(bx, by, bz) * A.bstride;
+            double *base = A.ring + slot * level + (((int64_t)bz * Py + by) * Px + bx) * bstride;
             const int px = lz * Wy + ly, py = lz * Wx + lx, pz = ly * Wx + lx;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double u = zc[c];
-                if (lx == 0) base[A.foff[0] + c * A.psz[0] + px] = u;
-                if (lx == Wx - 1) base[A.foff[1] + c * A.psz[0] + px] = u;
-                if (ly == 0) base[A.foff[2] + c * A.psz[1] + py] = u;
-                if (ly == Wy - 1) base[A.foff[3] + c * A.psz[1] + py] = u;
-                if (lz == 0) base[A.foff[4] + c * A.psz[2] + pz] = u;
-                if (lz == Wz - 1) base[A.foff[5] + c * A.psz[2] + pz] = u;
+                const double u = c == 0 ? zc0 : (c == 1 ? zc1 : zc2);
+                if (lx == 0) base[A.foff[0] + c * psz0 + px] = u;
+                if (lx == Wx - 1) base[A.foff[1] + c * psz0 + px] = u;
+                if (ly == 0) base[A.foff[2] + c * psz1 + py] = u;
+                if (ly == Wy - 1) base[A.foff[3] + c * psz1 + py] = u;
+                if (lz == 0) base[A.foff[4] + c * psz2 + pz] = u;
+                if (lz == Wz - 1) base[A.foff[5] + c * psz2 + pz] = u;
             }
         }
         if (more) {
             // plane z+1: interior, rims and z neighbour (loads issued one plane ago)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) pl[buf ^ 1][c][ty + 1][tx + 1] = zq[0][c];
+            pl[buf ^ 1][0][ty + 1][tx + 1] = znx[0];
+            pl[buf ^ 1][1][ty + 1][tx + 1] = znx[1];
+            pl[buf ^ 1][2][ty + 1][tx + 1] = znx[2];
             finish_rims(buf ^ 1);
-            hz_lo = hz_hi = false;
-            if (zk > 0) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) hz[c] = ext(zk, zv0[c], zv1[c]);
-                hz_lo = zside == 0;
-                hz_hi = zside == 1;
-            }
+            take_z();
             if (z + 2 < Z1) issue(z + 2);
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            zm[c] = zc[c];
-            zc[c] = zq[0][c];
-#pragma unroll
-            for (int q = 0; q < PF; ++q) zq[q][c] = zq[q + 1][c];
+        zm0 = zc0; zm1 = zc1; zm2 = zc2;
+        zc0 = znx[0]; zc1 = znx[1]; zc2 = znx[2];
+        ++lz;
+    };
+    int z = Z0;
+    if (PF == 1) {
+        for (; z + 2 <= Z1; z += 2) {
+            body(z, qa, qb);
+            body(z + 1, qb, qa);
         }
+        if (z < Z1) body(z, qa, qb);
+    } else {
+        for (; z + 3 <= Z1; z += 3) {
+            body(z, qa, qc);
+            body(z + 1, qb, qa);
+            body(z + 2, qc, qb);
+        }
+        if (z < Z1) body(z++, qa, qc);
+        if (z < Z1) body(z, qb, qa);
     }
 }
 
@@ -670,6 +735,8 @@ at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, i
     const int TYv = k3_rows(var);
     const int64_t gx = (A.nx + TX - 1) / TX, gy = (A.ny + TYv - 1) / TYv;
     A.ZC = zchunk(A.nz, gx * gy);
+    const bool aligned_var = (var >= 6 && var <= 8) || var >= 12;
+    if (aligned_var && A.ZC > (kZB - 2) * A.Wz) A.ZC = (kZB - 2) * A.Wz;   // LDS delay table
     const int64_t gz = (A.nz + A.ZC - 1) / A.ZC;
     const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)gz), block(TX, TYv);
     hipStream_t st = at_ctx_stream(ctx);
@@ -684,8 +751,8 @@ at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, i
     case 7: hipLaunchKernelGGL((k_step3d_aligned<16, 2, 1>), grid, block, 0, st, A); break;
     case 8: hipLaunchKernelGGL((k_step3d_aligned<4, 6, 1>), grid, block, 0, st, A); break;
     case 12: hipLaunchKernelGGL((k_step3d_aligned<8, 2, 2>), grid, block, 0, st, A); break;
-    case 13: hipLaunchKernelGGL((k_step3d_aligned<8, 2, 4>), grid, block, 0, st, A); break;
-    case 14: hipLaunchKernelGGL((k_step3d_aligned<16, 1, 4>), grid, block, 0, st, A); break;
+    case 13: hipLaunchKernelGGL((k_step3d_aligned<8, 3, 2>), grid, block, 0, st, A); break;
+    case 14: hipLaunchKernelGGL((k_step3d_aligned<16, 1, 2>), grid, block, 0, st, A); break;
     case 9: hipLaunchKernelGGL((k_step3d_direct<4>), grid, block, 0, st, A); break;
     case 10: hipLaunchKernelGGL((k_step3d_direct<8>), grid, block, 0, st, A); break;
     default: hipLaunchKernelGGL((k_step3d_direct<16>), grid, block, 0, st, A); break;
