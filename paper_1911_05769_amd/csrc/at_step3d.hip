@@ -331,22 +331,38 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
         }
     }
 
-    // roles
-    const bool xr_role = ty == 0 && tx < 2 * TY;
-    const int xr_row = tx >> 1, xr_side = tx & 1;
-    const int xr_x = xr_side ? wrap32(X0 + TX, nx) : wrap32(X0 - 1, nx);
-    const int xr_ly = (Y0 + xr_row) - by * Wy;
-    const bool xr_face = xr_side ? fxh : fxl;
-    const int xr_col = xr_side ? TX + 1 : 0;
-    const int64_t xr_blk = ((int64_t)wrap32(bx + (xr_side ? 1 : -1), A.Px)) +
-                           (int64_t)by * Px;                       // + bz * Py * Px
-    const int64_t xr_foff = xr_side ? A.foff[0] : A.foff[1];
-    const bool yr_role = ty < 2;
-    const int yr_y = ty ? wrap32(Y0 + TY, ny) : wrap32(Y0 - 1, ny);
-    const bool yr_face = ty ? fyh : fyl;
-    const int yr_row = ty ? TY + 1 : 0;
-    const int64_t yr_blk = (int64_t)bx + (int64_t)wrap32(by + (ty ? 1 : -1), A.Py) * Px;
-    const int64_t yr_foff = ty ? A.foff[2] : A.foff[3];
+    // rim roles, at most one per lane: waves 0 and 1 the low / high y-rim
+    // rows, lanes 0..2TY-1 of wave 2 the x rims (row tx/2, low / high side
+    // by tx&1); a role fixes the face, the neighbour block, the position in
+    // the face plane, the field column and the LDS slot of the rim value
+    const bool y_role = ty < 2;
+    const bool x_role = ty == 2 && tx < 2 * TY;
+    const bool rim_role = y_role || x_role;
+    int r_fidx = 0, r_lzmul = 0, r_lds = 0;
+    bool r_face = false;
+    int64_t r_blk = 0, r_foff = 0, r_pos = 0, r_cring = 0, r_field = 0;
+    if (y_role) {
+        r_fidx = 2 + ty;
+        r_face = ty ? fyh : fyl;
+        r_blk = (int64_t)bx + (int64_t)wrap32(by + (ty ? 1 : -1), A.Py) * Px;
+        r_foff = ty ? A.foff[2] : A.foff[3];
+        r_pos = lx;
+        r_lzmul = Wx;
+        r_cring = A.psz[1];
+        r_field = (int64_t)(ty ? wrap32(Y0 + TY, ny) : wrap32(Y0 - 1, ny)) * nx + x;
+        r_lds = (ty ? TY + 1 : 0) * (TX + 2) + tx + 1;
+    } else if (x_role) {
+        const int row = tx >> 1, side = tx & 1;
+        r_fidx = side;
+        r_face = side ? fxh : fxl;
+        r_blk = (int64_t)wrap32(bx + (side ? 1 : -1), A.Px) + (int64_t)by * Px;
+        r_foff = side ? A.foff[0] : A.foff[1];
+        r_pos = (Y0 + row) - by * Wy;
+        r_lzmul = Wy;
+        r_cring = A.psz[0];
+        r_field = (int64_t)(Y0 + row) * nx + (side ? wrap32(X0 + TX, nx) : wrap32(X0 - 1, nx));
+        r_lds = (row + 1) * (TX + 2) + (side ? TX + 1 : 0);
+    }
     const int64_t z_blk = (int64_t)bx + (int64_t)by * Px;
     const int64_t zlo_foff = A.foff[5], zhi_foff = A.foff[4];
     const int64_t psz0 = A.psz[0], psz1 = A.psz[1], psz2 = A.psz[2];
@@ -380,46 +396,40 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
     }
     __syncthreads();                                      // kdl ready
 
-    // loads of plane p's rims and z neighbour, consumed one plane later
-    Nb3 xr{}, yr{}, zr{};
-    int zside = 0;
+    // loads of plane p's rim values, consumed one plane later
+    Nb3 rr{};
     auto issue = [&](int p) {
         const int bz = p / Wz, lz = p - bz * Wz;
-        const int8_t *kc = kdl + 6 * (bz - bz0);
-        const int64_t zoff = (int64_t)bz * PyPx;
-        if (xr_role) {
-            const int k = xr_face ? kc[xr_side] : 0;
-            const int64_t off = (xr_blk + zoff) * bstride + xr_foff + lz * Wy + xr_ly;
-            xr = load_nb3(A.ring, U0, k, stale, lvl(k) + off, lvl(k + 1) + off, psz0,
-                          (int64_t)p * plane + (Y0 + xr_row) * nx + xr_x, npt);
+        if (rim_role) {
+            const int k = r_face ? kdl[6 * (bz - bz0) + r_fidx] : 0;
+            const int64_t off = (r_blk + (int64_t)bz * PyPx) * bstride + r_foff +
+                                (int64_t)lz * r_lzmul + r_pos;
+            rr = load_nb3(A.ring, U0, k, stale, lvl(k) + off, lvl(k + 1) + off, r_cring,
+                          (int64_t)p * plane + r_field, npt);
         }
-        if (yr_role) {
-            const int k = yr_face ? kc[2 + ty] : 0;
-            const int64_t off = (yr_blk + zoff) * bstride + yr_foff + lz * Wx + lx;
-            yr = load_nb3(A.ring, U0, k, stale, lvl(k) + off, lvl(k + 1) + off, psz1,
-                          (int64_t)p * plane + yr_y * nx + x, npt);
+    };
+    // plane p's rim values into LDS buffer bf
+    auto finish_rims = [&](int bf) {
+        if (rim_role) {
+            (&pl[bf][0][0][0])[r_lds] = at_h(rr.k, stale, rr.a0, rr.b0);
+            (&pl[bf][1][0][0])[r_lds] = at_h(rr.k, stale, rr.a1, rr.b1);
+            (&pl[bf][2][0][0])[r_lds] = at_h(rr.k, stale, rr.a2, rr.b2);
         }
+    };
+    // z neighbour of plane p across a block face (uniform over the tile):
+    // loads issued at the start of the step before, consumed at its end
+    Nb3 zr{};
+    int zside = 0;
+    auto issue_z = [&](int p) {
+        const int bz = p / Wz, lz = p - bz * Wz;
         zside = lz == 0 ? 0 : 1;
-        const int k = (lz == 0 || lz == Wz - 1) ? kc[4 + zside] : 0;   // uniform over the tile
+        const int k = (lz == 0 || lz == Wz - 1) ? kdl[6 * (bz - bz0) + 4 + zside] : 0;
         zr.k = k;
         if (k > 0) {
             const int nbz = wrap32(bz + (zside ? 1 : -1), A.Pz);
             const int64_t off = (z_blk + (int64_t)nbz * PyPx) * bstride +
                                 (zside ? zhi_foff : zlo_foff) + ly * Wx + lx;
             zr = load_nb3(A.ring, U0, k, stale, lvl(k) + off, lvl(k + 1) + off, psz2, 0, npt);
-        }
-    };
-    // plane p's rims into LDS buffer bf
-    auto finish_rims = [&](int bf) {
-        if (xr_role) {
-            pl[bf][0][xr_row + 1][xr_col] = at_h(xr.k, stale, xr.a0, xr.b0);
-            pl[bf][1][xr_row + 1][xr_col] = at_h(xr.k, stale, xr.a1, xr.b1);
-            pl[bf][2][xr_row + 1][xr_col] = at_h(xr.k, stale, xr.a2, xr.b2);
-        }
-        if (yr_role) {
-            pl[bf][0][yr_row][tx + 1] = at_h(yr.k, stale, yr.a0, yr.b0);
-            pl[bf][1][yr_row][tx + 1] = at_h(yr.k, stale, yr.a1, yr.b1);
-            pl[bf][2][yr_row][tx + 1] = at_h(yr.k, stale, yr.a2, yr.b2);
         }
     };
 
@@ -435,6 +445,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
             hz_hi = zside == 1;
         }
     };
+    issue_z(Z0);
     issue(Z0);
     pl[0][0][ty + 1][tx + 1] = zc0;
     pl[0][1][ty + 1][tx + 1] = zc1;
@@ -458,6 +469,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
 #pragma unroll
             for (int c = 0; c < 3; ++c) zld[c] = U0[c * npt + o];
         }
+        if (more) issue_z(z + 1);
         __syncthreads();
         const double ux = zc0, uy = zc1, uz = zc2;
         double *out = A.uout + (int64_t)z * plane + col;
@@ -749,7 +761,7 @@ at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, i
     case 5: hipLaunchKernelGGL((k_step3d<16, 2, 2>), grid, block, 0, st, A); break;
     case 6: hipLaunchKernelGGL((k_step3d_aligned<8, 4, 1>), grid, block, 0, st, A); break;
     case 7: hipLaunchKernelGGL((k_step3d_aligned<16, 2, 1>), grid, block, 0, st, A); break;
-    case 8: hipLaunchKernelGGL((k_step3d_aligned<4, 6, 1>), grid, block, 0, st, A); break;
+    case 8: hipLaunchKernelGGL((k_step3d_aligned<4, 5, 1>), grid, block, 0, st, A); break;
     case 12: hipLaunchKernelGGL((k_step3d_aligned<8, 2, 2>), grid, block, 0, st, A); break;
     case 13: hipLaunchKernelGGL((k_step3d_aligned<8, 3, 2>), grid, block, 0, st, A); break;
     case 14: hipLaunchKernelGGL((k_step3d_aligned<16, 1, 2>), grid, block, 0, st, A); break;
