@@ -77,6 +77,7 @@ SIGNATURES = {
     "at_run": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64]),
     "at_autotune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P]),
     "at_set_fuse": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "at_set_adjoint_fuse": (ctypes.c_int, [_P, ctypes.c_int32]),
     "at_set_variant": (ctypes.c_int, [_P, ctypes.c_int32]),
     "at_query": (ctypes.c_int, [_P, _P, _P, _P]),
     "at_delays_copy": (ctypes.c_int, [_P, _P]),
@@ -257,6 +258,10 @@ class Stepper:
 
     def set_fuse(self, s: int):
         _check(lib().at_set_fuse(self._ctx, int(s)), "at_set_fuse")
+
+    def set_adjoint_fuse(self, s: int):
+        """Reverse steps per adjoint launch: 0 automatic, 1 one step per launch."""
+        _check(lib().at_set_adjoint_fuse(self._ctx, int(s)), "at_set_adjoint_fuse")
 
     def set_variant(self, v: int):
         _check(lib().at_set_variant(self._ctx, int(v)), "at_set_variant")

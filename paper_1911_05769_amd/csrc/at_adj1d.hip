@@ -246,9 +246,324 @@ __global__ __launch_bounds__(kThreads) void k_adj1d(Adj1D a)
     }
 }
 
+
+__device__ __forceinline__ int64_t fdiv(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+constexpr int kPPF = 8;                       // points per thread, fused reverse kernel
+
+// S reverse steps in one launch.  The workgroup's region is its owned chunk
+// plus S*h points on each side; every reverse step reads lambda and u within
+// h points (across a tile face: the mu of that face, computed from points
+// within h of it), so after S steps the owned points are exact while the
+// rims have gone stale, as in the forward fused launches.  lambda stays in
+// registers; each step reads its level of u (the recomputed segment), the
+// next level's loads in flight meanwhile.  In LDS: the delay rows of the
+// launch's gather window, the record-mode ring levels that the forward
+// halos of these steps read, and the mu of every face of the region for
+// levels nt-S .. nt-1 (computed here) and nt .. nt+L+m-2 (from the mu ring).
+// Each point's lambda^n is summed in the same order as the one-step kernel.
+template <int ORDER, bool LINEAR>
+__global__ __launch_bounds__(kThreads) void k_adj1d_fused(AdjF a)
+{
+    constexpr int H = ORDER / 2;
+    constexpr int M = (ORDER == 2) ? 2 : 3;
+    constexpr int NS = 2 * H;
+    constexpr int PPT = kPPF;
+    extern __shared__ double lds[];
+    const int S = a.S, NT = a.NT;
+    const int DW = a.L + M - 1;               // gather window beyond the step, in levels
+    const int LV = S + DW;                    // levels held per history table
+    double *xch = lds;                                        // [2][2 arrays][2H][kThreads]
+    double *eh = xch + 2 * 2 * NS * kThreads;                 // [LV][NT][2][H]: u edges, levels nt-S-DW ..
+    double *muh = eh + (size_t)LV * NT * 2 * H;               // [LV][NT][2][H]: mu, levels nt-S ..
+    int8_t *kd = reinterpret_cast<int8_t *>(muh + (size_t)LV * NT * 2 * H);   // [LV][NT][2]: rows nt-S ..
+
+    const int tid = threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.x * a.CH;
+    const int owned = (int)((a.N - c0 < a.CH) ? (a.N - c0) : a.CH);
+    const int E = a.RL + owned + S * H;                       // region length
+    const int64_t G0 = c0 - a.RL;                             // multiple of PPT
+    const int rp0 = tid * PPT;
+    const int64_t Gt = G0 + rp0;
+    const int64_t tdiv = fdiv(Gt, a.W);
+    const int o0 = (int)(Gt - tdiv * a.W);                    // multiple of PPT
+    const int tl0 = (int)(tdiv - fdiv(G0, a.W));
+    int64_t tp0 = tdiv % a.P;
+    if (tp0 < 0) tp0 += a.P;
+    const bool in_region = rp0 < E;
+    const bool lo_edge = o0 == 0 && in_region;
+    const bool hi_edge = o0 + PPT == a.W && in_region;
+    const bool owns = rp0 >= a.RL && rp0 < a.RL + owned;
+    int64_t gb = Gt % a.N;                                    // a thread's points never straddle the wrap
+    if (gb < 0) gb += a.N;
+    const Partials<ORDER> pd = partials<ORDER>(a.c1, a.c2);
+    const bool stale = a.stale != 0;
+    const int64_t F = 2 * a.P;
+    const int64_t nlo = a.nt - S;                             // lowest level computed here
+
+    // ---- LDS tables
+    {
+        int64_t tb = fdiv(G0, a.W) % a.P;
+        if (tb < 0) tb += a.P;
+        const int nk = LV * NT * 2;
+        for (int e = tid; e < nk; e += kThreads) {
+            const int side = e & 1;
+            const int tl = (e >> 1) % NT;
+            const int r = (e >> 1) / NT;
+            const int64_t n2 = nlo + r;
+            const int64_t tp = (tb + tl) % a.P;
+            kd[e] = n2 < a.nsteps_total ? a.delays[n2 * F + 2 * tp + side] : (int8_t)0;
+        }
+        const int nh = LV * NT * 2 * H;
+        for (int e = tid; e < nh; e += kThreads) {
+            const int q = e % H;
+            const int side = (e / H) & 1;
+            const int tl = (e / (2 * H)) % NT;
+            const int r = (e / (2 * H)) / NT;
+            const int64_t tp = (tb + tl) % a.P;
+            const int64_t lev = nlo - DW + r;                 // u edge level
+            if (lev >= 0)
+                eh[e] = a.ring[((lev * a.P + tp) * 2 + side) * H + q];
+            const int64_t n2 = nlo + r;                       // mu level
+            if (n2 >= a.nt && n2 < a.nsteps_total) {
+                const int64_t ms = n2 % a.Rmu;
+                muh[e] = a.mu[((ms * a.P + tp) * 2 + side) * H + q];
+            }
+        }
+    }
+
+    // ---- lambda^{nt} of the thread's points
+    double lam[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) lam[j] = in_region ? a.lam_in[gb + j] : 0.0;
+
+    // P_s(u) = dt*(nu*g2[s] - a*g1[s]) for a compile-time slot s
+    auto Ps = [&](int s, double u) -> double {
+        const double adv = LINEAR ? a.cadv : u;
+        return a.dt * (a.nu * pd.g2[s] - adv * pd.g1[s]);
+    };
+
+    Acc gacc{0.0, 0.0};
+    // one reverse step: level n = nt-1-t from lambda^{n+1} (lam) and u^n (uc);
+    // the loads of u^{n-1} go to un
+    auto rstep = [&](int t, double (&uc)[PPT], double (&un)[PPT]) {
+        const int64_t n = a.nt - 1 - t;
+        {   // unconditional (a level inside the segment), so that the wait for uc
+            // below leaves these loads in flight
+            const int64_t nn = t + 1 < S ? n - 1 : n;
+            const double *src = a.seg + (nn - a.seg_n0) * a.N + gb;
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) un[j] = src[j];
+        }
+        // ---- exchange lambda^{n+1} and u^n edges with the neighbouring threads
+        double *buf = xch + (t & 1) * 2 * NS * kThreads;
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            buf[(0 * NS + q) * kThreads + tid] = lam[q];
+            buf[(0 * NS + H + q) * kThreads + tid] = lam[PPT - H + q];
+            buf[(1 * NS + q) * kThreads + tid] = uc[q];
+            buf[(1 * NS + H + q) * kThreads + tid] = uc[PPT - H + q];
+        }
+        __syncthreads();
+        double llo[H], lhi[H], ulo[H], uhi[H];   // raw neighbours: points -H..-1 and PPT..PPT+H-1
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
+            llo[q] = tid > 0 ? buf[(0 * NS + H + q) * kThreads + tid - 1] : 0.0;
+            ulo[q] = tid > 0 ? buf[(1 * NS + H + q) * kThreads + tid - 1] : 0.0;
+            lhi[q] = tid < kThreads - 1 ? buf[(0 * NS + q) * kThreads + tid + 1] : 0.0;
+            uhi[q] = tid < kThreads - 1 ? buf[(1 * NS + q) * kThreads + tid + 1] : 0.0;
+        }
+        // ---- u window with the forward AT halo across the tile faces
+        double uw[PPT + 2 * H];
+#pragma unroll
+        for (int q = 0; q < H; ++q) { uw[q] = ulo[q]; uw[PPT + H + q] = uhi[q]; }
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) uw[H + j] = uc[j];
+        const int krow = (int)(n - nlo);
+        if (lo_edge || hi_edge) {
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                // region ends: no source tile inside the tables (outside the owned cone)
+                if (side == 0 ? !(lo_edge && tid > 0) : !(hi_edge && tid < kThreads - 1)) continue;
+                const int kk = kd[(krow * NT + tl0) * 2 + side];
+                if (kk > 0) {
+                    const int stl = side == 0 ? tl0 - 1 : tl0 + 1;
+#pragma unroll
+                    for (int q = 0; q < H; ++q) {
+                        double vv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int jj = 0; jj < M; ++jj) {
+                            if (jj == 0 || !stale) {
+                                const int64_t lev = n - kk - jj;
+                                vv[jj] = eh[((((int)(lev - (nlo - DW))) * NT + stl) * 2 + (1 - side)) * H + q];
+                            }
+                        }
+                        const double hv = extrap(kk, stale, vv[0], vv[1], vv[2], M);
+                        if (side == 0) uw[q] = hv;
+                        else uw[PPT + H + q] = hv;
+                    }
+                }
+            }
+        }
+        // lambda and raw u at window index i (-H .. PPT+H-1), compile-time i
+        auto lat = [&](int i) -> double { return i < 0 ? llo[H + i] : (i >= PPT ? lhi[i - PPT] : lam[i]); };
+        auto uat = [&](int i) -> double { return i < 0 ? ulo[H + i] : (i >= PPT ? uhi[i - PPT] : uc[i]); };
+        // mu^n of this step for the face a point feeds, from the raw window
+        auto mu_lo = [&](int q) -> double {         // face of the next tile, low side: its first h points
+            double m = 0.0;
+#pragma unroll
+            for (int e = 0; e < H; ++e)
+                if (e <= q) m += lat(PPT + e) * Ps(q - e, uat(PPT + e));
+            return m;
+        };
+        auto mu_hi = [&](int q) -> double {         // face of the previous tile, high side: its last h points
+            double m = 0.0;
+#pragma unroll
+            for (int e = 0; e < H; ++e)
+                if (e <= H - 1 - q) m += lat(-1 - e) * Ps(H + q + e, uat(-1 - e));
+            return m;
+        };
+        double res[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            const double u = uc[j];
+            double nb[NS];
+#pragma unroll
+            for (int q = 0; q < H; ++q) { nb[q] = uw[j + q]; nb[H + q] = uw[j + H + 1 + q]; }
+            double D1, D2;
+            if constexpr (ORDER == 2) {
+                D1 = (nb[1] - nb[0]) * a.c1;
+                D2 = ((nb[1] - 2.0 * u) + nb[0]) * a.c2;
+            } else {
+                D1 = (8.0 * (nb[2] - nb[1]) - (nb[3] - nb[0])) * a.c1;
+                D2 = ((16.0 * (nb[2] + nb[1]) - 30.0 * u) - (nb[3] + nb[0])) * a.c2;
+            }
+            const double lg = lam[j];
+            const double du = 1.0 + a.dt * (a.nu * pd.g2u - (LINEAR ? 0.0 : D1));
+            double acc = lg * du;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int d = (s < H) ? -(H - s) : (s - H + 1);
+                const int i = j - d;
+                const bool same = (i >= 0 || !lo_edge) && (i < PPT || !hi_edge);
+                if (same) acc += lat(i) * Ps(s, uat(i));
+            }
+            // delayed halo contributions gathered over steps n .. n+L+m-1
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                const bool feeds = side == 0 ? (hi_edge && tid < kThreads - 1 && j >= PPT - H)
+                                             : (lo_edge && tid > 0 && j < H);
+                if (!feeds) continue;
+                const int stl = side == 0 ? tl0 + 1 : tl0 - 1;
+                const int fs = side == 0 ? 0 : 1;
+                const int q = side == 0 ? j - (PPT - H) : j;
+                for (int dn = 0; dn <= DW; ++dn) {
+                    const int64_t n2 = n + dn;
+                    if (n2 >= a.nsteps_total) break;
+                    const int r2 = krow + dn;
+                    const int kk = kd[(r2 * NT + stl) * 2 + fs];
+                    const int jw = dn - kk;
+                    const int need = (kk == 0 || stale) ? 1 : M;
+                    if (jw < 0 || jw >= need) continue;
+                    const double m = dn == 0 ? (side == 0 ? mu_lo(q) : mu_hi(q))
+                                             : muh[((r2 * NT + stl) * 2 + fs) * H + q];
+                    acc += hweight(kk, stale, jw, M) * m;
+                }
+            }
+            res[j] = acc;
+            if (owns) acc_add(gacc, lg * (a.dt * D2));
+        }
+        // ---- mu^n of this tile's faces: LDS for later steps, the ring for later launches
+        if (lo_edge || hi_edge) {
+            const int64_t ms = n % a.Rmu;
+#pragma unroll
+            for (int q = 0; q < H; ++q) {
+                if (lo_edge) {                        // own first h points feed the low face
+                    double m = 0.0;
+#pragma unroll
+                    for (int e = 0; e < H; ++e)
+                        if (e <= q) m += lam[e] * Ps(q - e, uc[e]);
+                    muh[((krow * NT + tl0) * 2 + 0) * H + q] = m;
+                    if (owns) a.mu[((ms * a.P + tp0) * 2 + 0) * H + q] = m;
+                }
+                if (hi_edge) {                        // own last h points feed the high face
+                    double m = 0.0;
+#pragma unroll
+                    for (int e = 0; e < H; ++e)
+                        if (e <= H - 1 - q) m += lam[PPT - 1 - e] * Ps(H + q + e, uc[PPT - 1 - e]);
+                    muh[((krow * NT + tl0) * 2 + 1) * H + q] = m;
+                    if (owns) a.mu[((ms * a.P + tp0) * 2 + 1) * H + q] = m;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) lam[j] = res[j];
+    };
+
+    double ua[PPT], ub[PPT];
+    {
+        const double *src = a.seg + (a.nt - 1 - a.seg_n0) * a.N + gb;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) ua[j] = src[j];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) ub[j] = 0.0;
+    }
+    __syncthreads();                          // LDS tables ready
+    int t = 0;
+    for (; t + 2 <= S; t += 2) {
+        rstep(t, ua, ub);
+        rstep(t + 1, ub, ua);
+    }
+    if (t < S) rstep(t, ua, ub);
+
+    if (owns) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) a.lam_out[gb + j] = lam[j];
+    }
+    __shared__ double red[kThreads / 64][2];
+    gacc = wave_acc(gacc);
+    const int lane = tid & 63, wv = tid >> 6;
+    if (lane == 0) { red[wv][0] = gacc.s; red[wv][1] = gacc.c; }
+    __syncthreads();
+    if (tid == 0) {
+        Acc Sg{a.gnu[blockIdx.x * 2], a.gnu[blockIdx.x * 2 + 1]};
+        for (int q = 0; q < kThreads / 64; ++q) acc_merge(Sg, Acc{red[q][0], red[q][1]});
+        a.gnu[blockIdx.x * 2] = Sg.s;
+        a.gnu[blockIdx.x * 2 + 1] = Sg.c;
+    }
+}
+
 }  // namespace
 
 int adj1d_points_per_block() { return kCHA; }
+
+int adj1d_fused_points_per_thread() { return kPPF; }
+
+size_t adj1d_fused_lds_bytes(int order, int S, int NT, int L)
+{
+    const int H = order / 2, M = order == 2 ? 2 : 3;
+    const size_t LV = (size_t)S + L + M - 1;
+    const size_t dbl = (size_t)2 * 2 * 2 * H * kThreads + 2 * LV * NT * 2 * H;
+    return 8 * dbl + ((LV * NT * 2 + 7) / 8) * 8;
+}
+
+hipError_t launch_adj1d_fused(const AdjF &a, int order, bool linear, int64_t nblocks, size_t lds,
+                              hipStream_t st)
+{
+    dim3 grid((unsigned)nblocks), block(kThreads);
+    if (order == 2) {
+        if (linear) hipLaunchKernelGGL((k_adj1d_fused<2, true>), grid, block, lds, st, a);
+        else hipLaunchKernelGGL((k_adj1d_fused<2, false>), grid, block, lds, st, a);
+    } else {
+        if (linear) hipLaunchKernelGGL((k_adj1d_fused<4, true>), grid, block, lds, st, a);
+        else hipLaunchKernelGGL((k_adj1d_fused<4, false>), grid, block, lds, st, a);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_adj1d(const Adj1D &a, int order, bool linear, int64_t nblocks, hipStream_t st)
 {

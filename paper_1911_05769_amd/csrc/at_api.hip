@@ -162,6 +162,7 @@ struct at_ctx {
     int64_t n;
     int fuse;
     int variant;     // 3D kernel variant (tile rows, prefetch depth, register budget)
+    int adj_fuse = 0;   // reverse steps per adjoint launch: 0 automatic, 1 one-step kernel
 };
 
 namespace {
@@ -181,7 +182,7 @@ int64_t adj_blocks(const Derived &d)
 at_status make_layout(const at_config *c, const Derived &d, Layout &L)
 {
     L.R = ring_levels(c, d);
-    L.Rmu = c->L + d.m;
+    L.Rmu = c->L + d.m + kMaxFuse;   // levels a fused reverse launch writes and reads stay distinct
     uint64_t off = 0;
     L.delays = off;
     off = align_up(off + (uint64_t)c->nsteps_max * (uint64_t)d.F);
@@ -325,6 +326,41 @@ int max_fuse(const at_ctx *c)
     return c->d.dim == 1 ? max_fuse_1d(c->d) : at3_max_fuse(c);
 }
 
+// Region of a fused reverse launch of s steps (8 points per thread, aligned)
+struct RegionAdj {
+    int64_t RL, CH;
+    int NT;
+};
+
+RegionAdj region_adj(const Derived &d, int s)
+{
+    const int ppf = adj1d_fused_points_per_thread();
+    const int64_t reg = (int64_t)kThreads * ppf;
+    RegionAdj r;
+    r.RL = ((int64_t)s * d.h + ppf - 1) / ppf * ppf;
+    r.CH = (reg - r.RL - (int64_t)s * d.h) / ppf * ppf;
+    if (r.CH > d.N) r.CH = d.N;
+    r.NT = (int)((reg - 1) / d.W + 2);
+    return r;
+}
+
+// Reverse steps per launch: 0 when the tiles do not fit the fused kernel,
+// else the most (up to kMaxFuse) that keep the owned chunk at least one
+// one-step block and the LDS tables within 64 KiB
+int adj_fuse_max(const Derived &d, int L)
+{
+    const int ppf = adj1d_fused_points_per_thread();
+    if (d.W % ppf != 0) return 0;
+    int best = 0;
+    for (int s = 1; s <= kMaxFuse; ++s) {
+        const RegionAdj r = region_adj(d, s);
+        if (r.CH < std::min<int64_t>(adj1d_points_per_block(), d.N)) break;
+        if (adj1d_fused_lds_bytes(d.order, s, r.NT, L) > 64 * 1024) break;
+        best = s;
+    }
+    return best;
+}
+
 }  // namespace
 
 extern "C" {
@@ -418,6 +454,22 @@ at_status at_set_fuse(at_ctx *c, int32_t s)
     const int mf = max_fuse(c);
     if (s > mf) return fail(AT_ERR_ARG, "fuse_steps %d exceeds the limit %d of this grid", s, mf);
     c->fuse = s;
+    return AT_OK;
+}
+
+at_status at_set_adjoint_fuse(at_ctx *c, int32_t s)
+{
+    if (!c) return fail(AT_ERR_ARG, "null context");
+    if (s < 0 || s > kMaxFuse) return fail(AT_ERR_ARG, "adjoint steps per launch must be in 0..%d",
+                                           kMaxFuse);
+    if (s > 1) {
+        if (c->d.dim != 1) return fail(AT_ERR_ARG, "the adjoint is 1D only");
+        const int mf = adj_fuse_max(c->d, c->cfg.L);
+        if (s > mf)
+            return fail(AT_ERR_ARG, "%d reverse steps per launch exceed the limit %d of this grid",
+                        s, mf);
+    }
+    c->adj_fuse = s;
     return AT_OK;
 }
 
@@ -626,7 +678,45 @@ at_status at_adjoint(at_ctx *c, const double *lambda_T, double *grad_u0, double 
                 if (st) return st;
                 n += s;
             }
-            for (int64_t n = a1 - 1; n >= a0; --n) {
+            const int smax = adj_fuse_max(d, c->cfg.L);
+            const int sadj = c->adj_fuse == 0 ? smax : (c->adj_fuse == 1 ? 0 : c->adj_fuse);
+            for (int64_t nt = a1; sadj > 0 && nt > a0;) {
+                const int s = (int)std::min<int64_t>(sadj, nt - a0);
+                const RegionAdj rg = region_adj(d, s);
+                AdjF f;
+                f.lam_in = lcur;
+                f.lam_out = loth;
+                f.seg = c->seg;
+                f.ring = c->ring;
+                f.mu = c->mu;
+                f.delays = c->delays;
+                f.gnu = c->gnu;
+                f.N = N;
+                f.P = d.P;
+                f.W = d.W;
+                f.CH = rg.CH;
+                f.nt = nt;
+                f.seg_n0 = a0;
+                f.nsteps_total = nend;
+                f.S = s;
+                f.Rmu = c->lay.Rmu;
+                f.L = c->cfg.L;
+                f.stale = c->cfg.halo_mode;
+                f.RL = (int32_t)rg.RL;
+                f.NT = rg.NT;
+                f.nu = c->cfg.nu;
+                f.dt = c->cfg.dt;
+                f.c1 = d.c1[0];
+                f.c2 = d.c2[0];
+                f.cadv = c->cfg.adv_speed;
+                const int64_t nblocks = (N + rg.CH - 1) / rg.CH;   // <= ngnu (CH >= one-step block)
+                AT_HIP(launch_adj1d_fused(f, d.order, c->cfg.adv_mode == 1, nblocks,
+                                          adj1d_fused_lds_bytes(d.order, s, rg.NT, c->cfg.L),
+                                          c->st));
+                std::swap(lcur, loth);
+                nt -= s;
+            }
+            for (int64_t n = a1 - 1; sadj == 0 && n >= a0; --n) {
                 Adj1D a;
                 a.lam_in = lcur;
                 a.lam_out = loth;

@@ -51,6 +51,22 @@ struct Adj1D {
     double nu, dt, c1, c2, cadv;
 };
 
+// S reverse steps of the 1D stepper in one launch (tile width a multiple of
+// the points per thread): levels nt-1 .. nt-S over overlapped regions.
+struct AdjF {
+    const double *lam_in;     // lambda^{nt}
+    double *lam_out;          // lambda^{nt-S}
+    const double *seg;        // u levels: level n at seg + (n - seg_n0) * N
+    const double *ring;       // full edge history (record mode): [levels][P][2][h]
+    double *mu;               // halo adjoints: [Rmu][P][2][h], level n in slot n mod Rmu
+    const int8_t *delays;     // k[n][2P]
+    double *gnu;              // per-workgroup compensated dJ/dnu: [nblocks][2]
+    int64_t N, P, W, CH;
+    int64_t nt, seg_n0, nsteps_total;
+    int32_t S, Rmu, L, stale, RL, NT;
+    double nu, dt, c1, c2, cadv;
+};
+
 // Neumaier-compensated accumulator used by the reductions.
 struct Acc {
     double s, c;
@@ -97,6 +113,10 @@ hipError_t launch_step1d_batch(const Step1D *descs, const int2 *tbl, int64_t nbl
 hipError_t launch_adj1d(const Adj1D &a, int order, bool linear, int64_t nblocks,
                         hipStream_t st);
 int adj1d_points_per_block();
+hipError_t launch_adj1d_fused(const AdjF &a, int order, bool linear, int64_t nblocks, size_t lds,
+                              hipStream_t st);
+int adj1d_fused_points_per_thread();
+size_t adj1d_fused_lds_bytes(int order, int S, int NT, int L);
 hipError_t launch_gnu_final(const double *part, int64_t nparts, double *out, hipStream_t st);
 hipError_t launch_stats(const double *u, int64_t n, double *part, double *out3, hipStream_t st);
 hipError_t launch_loss(const double *u, const double *t, double *lam, int64_t n, double *part,

@@ -246,6 +246,8 @@ ADJ_CASES = [
     ("o4_n1536_p12_L4", 1536, 12, 4, 4, 1, 0.01, 200, 64, {}),
     ("o2_stale_n1024_p8", 1024, 8, 2, 3, 0, 0.02, 100, 30, {"halo_mode": 1}),
     ("o2_linear_n1024_p4", 1024, 4, 2, 2, 0, 0.02, 100, 100, {"adv_mode": 1, "adv_speed": 0.5}),
+    ("o4_n1000_p8_w125_L2", 1000, 8, 4, 2, 0, 0.02, 90, 40, {}),      # one-step kernel only
+    ("o2_n4096_p512_w8_L3", 4096, 512, 2, 3, 1, 0.02, 150, 37, {}),    # narrow tiles
 ]
 
 
@@ -261,6 +263,17 @@ def test_adjoint_parity(gpu, case):
     lam = torch.empty(N, dtype=torch.float64, device="cuda")
     st.loss(u, dev(tgt), lam)
     g, gnu = st.adjoint(lam)
+    # one reverse step per launch and a small fused count give the same lambda bits
+    for s_adj in (1, 5):
+        try:
+            st.set_adjoint_fuse(s_adj)
+        except gpu.AtError as e:
+            assert s_adj > 1 and e.status == gpu.AT_ERR_ARG    # beyond this grid's limit
+            continue
+        g2, gnu2 = st.adjoint(lam)
+        assert torch.equal(g2, g), "adjoint fuse %d" % s_adj
+        assert abs(host(gnu2)[0] - host(gnu)[0]) <= 1e-13 * abs(host(gnu)[0])
+    st.set_adjoint_fuse(0)
     k = st.delays()
     kw = dict(stale=extra.get("halo_mode") == 1, linear=extra.get("adv_mode") == 1,
               adv_speed=extra.get("adv_speed", 0.0))
