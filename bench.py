@@ -393,8 +393,10 @@ def bench_adjoint(args, torch, at, I):
     tf = min(t[0] for t in times)
     ta = min(t[1] for t in times)
     pstep = N * nst
-    # reverse sweep: recompute (16 B) + reverse step (lambda in, u in, lambda out: 24 B)
-    gbps = pstep * 40.0 / ta / 1e9
+    # reverse sweep, algorithmic floor: every intermediate level of u is written
+    # once by the recompute and read once by the reverse steps (16 B per
+    # point-step); lambda stays on chip within a fused reverse launch
+    gbps = pstep * 16.0 / ta / 1e9
     eprint("[adjoint] forward %.2f ms, adjoint %.2f ms (%.0f GB/s algorithmic), J %.3e, "
            "dJ/dnu %.4e" % (tf * 1e3, ta * 1e3, gbps, float(J), float(gnu)))
     return {"value": pstep / (tf + ta), "unit": "point-steps/s (gradient)",

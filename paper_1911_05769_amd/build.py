@@ -36,7 +36,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     bad = [s for p, s in procs if p.wait() != 0]
     if bad:
         raise RuntimeError("hipcc failed for: " + ", ".join(bad))
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", LIB + ".tmp"]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined"] + objs + [
+        "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -253,7 +253,6 @@ __device__ __forceinline__ int64_t fdiv(int64_t a, int64_t b)
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 
-constexpr int kPPF = 8;                       // points per thread, fused reverse kernel
 
 // S reverse steps in one launch.  The workgroup's region is its owned chunk
 // plus S*h points on each side; every reverse step reads lambda and u within
@@ -266,13 +265,12 @@ constexpr int kPPF = 8;                       // points per thread, fused revers
 // halos of these steps read, and the mu of every face of the region for
 // levels nt-S .. nt-1 (computed here) and nt .. nt+L+m-2 (from the mu ring).
 // Each point's lambda^n is summed in the same order as the one-step kernel.
-template <int ORDER, bool LINEAR>
+template <int ORDER, bool LINEAR, int PPT>
 __global__ __launch_bounds__(kThreads) void k_adj1d_fused(AdjF a)
 {
     constexpr int H = ORDER / 2;
     constexpr int M = (ORDER == 2) ? 2 : 3;
     constexpr int NS = 2 * H;
-    constexpr int PPT = kPPF;
     extern __shared__ double lds[];
     const int S = a.S, NT = a.NT;
     const int DW = a.L + M - 1;               // gather window beyond the step, in levels
@@ -541,7 +539,22 @@ __global__ __launch_bounds__(kThreads) void k_adj1d_fused(AdjF a)
 
 int adj1d_points_per_block() { return kCHA; }
 
-int adj1d_fused_points_per_thread() { return kPPF; }
+hipError_t launch_adj1d_fused(const AdjF &a, int order, bool linear, int ppt, int64_t nblocks,
+                              size_t lds, hipStream_t st)
+{
+    dim3 grid((unsigned)nblocks), block(kThreads);
+#define AT_AF(O, LI, P) hipLaunchKernelGGL((k_adj1d_fused<O, LI, P>), grid, block, lds, st, a)
+    if (ppt != 4 && ppt != 8) return hipErrorInvalidValue;
+    if (order == 2) {
+        if (linear) { if (ppt == 8) AT_AF(2, true, 8); else AT_AF(2, true, 4); }
+        else { if (ppt == 8) AT_AF(2, false, 8); else AT_AF(2, false, 4); }
+    } else {
+        if (linear) { if (ppt == 8) AT_AF(4, true, 8); else AT_AF(4, true, 4); }
+        else { if (ppt == 8) AT_AF(4, false, 8); else AT_AF(4, false, 4); }
+    }
+#undef AT_AF
+    return hipGetLastError();
+}
 
 size_t adj1d_fused_lds_bytes(int order, int S, int NT, int L)
 {
@@ -549,20 +562,6 @@ size_t adj1d_fused_lds_bytes(int order, int S, int NT, int L)
     const size_t LV = (size_t)S + L + M - 1;
     const size_t dbl = (size_t)2 * 2 * 2 * H * kThreads + 2 * LV * NT * 2 * H;
     return 8 * dbl + ((LV * NT * 2 + 7) / 8) * 8;
-}
-
-hipError_t launch_adj1d_fused(const AdjF &a, int order, bool linear, int64_t nblocks, size_t lds,
-                              hipStream_t st)
-{
-    dim3 grid((unsigned)nblocks), block(kThreads);
-    if (order == 2) {
-        if (linear) hipLaunchKernelGGL((k_adj1d_fused<2, true>), grid, block, lds, st, a);
-        else hipLaunchKernelGGL((k_adj1d_fused<2, false>), grid, block, lds, st, a);
-    } else {
-        if (linear) hipLaunchKernelGGL((k_adj1d_fused<4, true>), grid, block, lds, st, a);
-        else hipLaunchKernelGGL((k_adj1d_fused<4, false>), grid, block, lds, st, a);
-    }
-    return hipGetLastError();
 }
 
 hipError_t launch_adj1d(const Adj1D &a, int order, bool linear, int64_t nblocks, hipStream_t st)

@@ -54,6 +54,7 @@ struct Layout {
 struct Derived {
     int dim, order, h, m;
     int L;          // delay bound
+    int fppt = 16;  // 1D: points per thread of the fused (aligned) launches
     int64_t N;      // total points
     int64_t F;      // faces
     int64_t nb;     // tiles / blocks
@@ -66,8 +67,26 @@ struct Derived {
 // and CH are multiples of PPT so every thread's points lie in one tile.
 struct Region1D {
     bool aligned;
+    int ppt;        // points per thread of the kernel that runs it
     int64_t RL, CH;
 };
+
+// Points per thread of the fused 1D launches: the most (16, 8, 4) that still
+// give every SIMD four waves of the grid and divide the tile width; 16 (the
+// unaligned kernel) when none divides it.
+int fused_ppt(const Derived &d)
+{
+    const int opts[3] = {16, 8, 4};
+    int pick = 0;
+    for (int i = 0; i < 3; ++i) {
+        const int p = opts[i];
+        if (d.W % p != 0) continue;
+        if (pick == 0) pick = p;
+        if (d.N >= (int64_t)4 * 1024 * 64 * p) return p;
+        pick = p;
+    }
+    return pick ? pick : 16;
+}
 
 at_status derive(const at_config *c, Derived &d)
 {
@@ -134,6 +153,7 @@ at_status derive(const at_config *c, Derived &d)
         at_status st = at3_check(c);
         if (st != AT_OK) return st;
     }
+    if (d.dim == 1) d.fppt = fused_ppt(d);
     return AT_OK;
 }
 
@@ -144,7 +164,7 @@ int max_fuse_1d(const Derived &d);
 // level of the run (the adjoint re-reads them).
 int ring_levels(const at_config *c, const Derived &d)
 {
-    const int smax = d.dim == 1 ? max_fuse_1d(d) : 1;
+    const int smax = d.dim == 1 ? kMaxFuse : 1;   // any points-per-thread choice
     int64_t R = c->L + d.m - 1 + smax;
     if (c->record) R = std::max<int64_t>(R, c->nsteps_max + 1);
     return (int)R;
@@ -200,7 +220,7 @@ at_status make_layout(const at_config *c, const Derived &d, Layout &L)
         off = align_up(off + 8ull * 2 * (uint64_t)d.N);
         L.mu = off;
         off = align_up(off + 8ull * (uint64_t)L.Rmu * (uint64_t)d.P * 2 * d.h);
-        L.ngnu = adj_blocks(d);
+        L.ngnu = (d.N + 255) / 256;   // >= the blocks of any reverse launch (chunks >= 256 points)
         L.gnu = off;
         off = align_up(off + 8ull * 2 * (uint64_t)L.ngnu);
     }
@@ -215,12 +235,13 @@ Region1D region_1d(const Derived &d, int s, bool allow_plain = true);
 // history fits in 64 KiB.
 int max_fuse_1d(const Derived &d)
 {
-    const int reg = kThreads * step1d_points_per_thread();
     int best = 1;
     for (int s = 2; s <= kMaxFuse; ++s) {
-        if (region_1d(d, s).CH < std::min<int64_t>(reg / 2, d.N)) break;
+        const Region1D rg = region_1d(d, s);
+        const int reg = kThreads * rg.ppt;
+        if (rg.CH < std::min<int64_t>(reg / 2, d.N)) break;
         const int NT = (int)((reg - 1) / d.W + 2);
-        if (step1d_lds_bytes(d.order, s, NT, d.L + d.m - 1) > 64 * 1024) break;
+        if (step1d_lds_bytes(d.order, s, NT, d.L + d.m - 1, rg.ppt) > 64 * 1024) break;
         best = s;
     }
     return best;
@@ -232,9 +253,10 @@ Region1D region_1d(const Derived &d, int s, bool allow_plain)
     // (not in the batched form, whose kernel keeps 16 points per thread)
     const int pplain = step1d_plain_points_per_thread();
     const bool plain = allow_plain && s == 1 && d.W % pplain == 0;
-    const int ppt = plain ? pplain : step1d_points_per_thread();
+    const int ppt = plain ? pplain : (d.W % d.fppt == 0 ? d.fppt : step1d_points_per_thread());
     const int64_t reg = (int64_t)kThreads * ppt;
     Region1D r;
+    r.ppt = ppt;
     r.aligned = d.W % ppt == 0;
     if (r.aligned) {
         r.RL = ((int64_t)s * d.h + ppt - 1) / ppt * ppt;
@@ -251,8 +273,8 @@ at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int 
                     double *levels = nullptr)
 {
     const Derived &d = c->d;
-    const int reg = kThreads * step1d_points_per_thread();
     const Region1D rg = region_1d(d, s);
+    const int reg = kThreads * rg.ppt;
     Step1D a;
     a.uin = uin;
     a.uout = uout;
@@ -282,8 +304,8 @@ at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int 
     a.A1 = a.dt * a.c1;
     a.A2 = a.dt * (a.nu * a.c2);
     const int64_t nblocks = (d.N + a.CH - 1) / a.CH;
-    AT_HIP(launch_step1d(a, d.order, c->cfg.adv_mode == 1, rg.aligned, c->cfg.arith == 1, nblocks,
-                         c->st));
+    AT_HIP(launch_step1d(a, d.order, c->cfg.adv_mode == 1, rg.aligned, c->cfg.arith == 1, rg.ppt,
+                         nblocks, c->st));
     return AT_OK;
 }
 
@@ -329,14 +351,25 @@ int max_fuse(const at_ctx *c)
 // Region of a fused reverse launch of s steps (8 points per thread, aligned)
 struct RegionAdj {
     int64_t RL, CH;
-    int NT;
+    int NT, ppt;
 };
+
+// Points per thread of the fused reverse launches (8 or 4: the larger one
+// that still gives every SIMD four waves and divides the tile width), 0 when
+// neither divides it
+int adj_ppt(const Derived &d)
+{
+    if (d.W % 8 == 0 && d.N >= (int64_t)4 * 1024 * 64 * 8) return 8;
+    if (d.W % 4 == 0) return 4;
+    return d.W % 8 == 0 ? 8 : 0;
+}
 
 RegionAdj region_adj(const Derived &d, int s)
 {
-    const int ppf = adj1d_fused_points_per_thread();
+    const int ppf = adj_ppt(d);
     const int64_t reg = (int64_t)kThreads * ppf;
     RegionAdj r;
+    r.ppt = ppf;
     r.RL = ((int64_t)s * d.h + ppf - 1) / ppf * ppf;
     r.CH = (reg - r.RL - (int64_t)s * d.h) / ppf * ppf;
     if (r.CH > d.N) r.CH = d.N;
@@ -345,16 +378,15 @@ RegionAdj region_adj(const Derived &d, int s)
 }
 
 // Reverse steps per launch: 0 when the tiles do not fit the fused kernel,
-// else the most (up to kMaxFuse) that keep the owned chunk at least one
-// one-step block and the LDS tables within 64 KiB
+// else the most (up to kMaxFuse) that keep the owned chunk at least half the
+// region (and 256 points) and the LDS tables within 64 KiB
 int adj_fuse_max(const Derived &d, int L)
 {
-    const int ppf = adj1d_fused_points_per_thread();
-    if (d.W % ppf != 0) return 0;
+    if (adj_ppt(d) == 0) return 0;
     int best = 0;
     for (int s = 1; s <= kMaxFuse; ++s) {
         const RegionAdj r = region_adj(d, s);
-        if (r.CH < std::min<int64_t>(adj1d_points_per_block(), d.N)) break;
+        if (r.CH < std::min<int64_t>(std::max<int64_t>(256, kThreads * r.ppt / 2), d.N)) break;
         if (adj1d_fused_lds_bytes(d.order, s, r.NT, L) > 64 * 1024) break;
         best = s;
     }
@@ -476,10 +508,18 @@ at_status at_set_adjoint_fuse(at_ctx *c, int32_t s)
 at_status at_set_variant(at_ctx *c, int32_t v)
 {
     if (!c) return fail(AT_ERR_ARG, "null context");
-    const int nv = c->d.dim == 1 ? 1 : at3_variants();
+    const int nv = c->d.dim == 1 ? 4 : at3_variants();
     if (v < 0 || v >= nv) return fail(AT_ERR_ARG, "variant must be in 0..%d", nv - 1);
     if (c->d.dim == 3 && !at3_variant_ok(&c->cfg, v))
         return fail(AT_ERR_ARG, "variant %d needs block widths that are multiples of its tile", v);
+    if (c->d.dim == 1) {
+        // 0: automatic; 1, 2, 3: 16, 8, 4 points per thread in fused launches
+        const int p = v == 0 ? 0 : (v == 1 ? 16 : (v == 2 ? 8 : 4));
+        if (p && c->d.W % p != 0)
+            return fail(AT_ERR_ARG, "variant %d needs a tile width divisible by %d", v, p);
+        c->d.fppt = p ? p : fused_ppt(c->d);
+        c->fuse = std::min(c->fuse, max_fuse(c));
+    }
     c->variant = v;
     return AT_OK;
 }
@@ -709,8 +749,8 @@ at_status at_adjoint(at_ctx *c, const double *lambda_T, double *grad_u0, double 
                 f.c1 = d.c1[0];
                 f.c2 = d.c2[0];
                 f.cadv = c->cfg.adv_speed;
-                const int64_t nblocks = (N + rg.CH - 1) / rg.CH;   // <= ngnu (CH >= one-step block)
-                AT_HIP(launch_adj1d_fused(f, d.order, c->cfg.adv_mode == 1, nblocks,
+                const int64_t nblocks = (N + rg.CH - 1) / rg.CH;   // <= ngnu (CH >= 256)
+                AT_HIP(launch_adj1d_fused(f, d.order, c->cfg.adv_mode == 1, rg.ppt, nblocks,
                                           adj1d_fused_lds_bytes(d.order, s, rg.NT, c->cfg.L),
                                           c->st));
                 std::swap(lcur, loth);
@@ -741,7 +781,7 @@ at_status at_adjoint(at_ctx *c, const double *lambda_T, double *grad_u0, double 
                 a.c1 = d.c1[0];
                 a.c2 = d.c2[0];
                 a.cadv = c->cfg.adv_speed;
-                AT_HIP(launch_adj1d(a, d.order, c->cfg.adv_mode == 1, c->lay.ngnu, c->st));
+                AT_HIP(launch_adj1d(a, d.order, c->cfg.adv_mode == 1, adj_blocks(d), c->st));
                 std::swap(lcur, loth);
             }
         }
@@ -852,7 +892,7 @@ at_status batch_tables(at_batch *b, int slot, int s, double *const *u, double *c
         a.A2 = a.dt * (a.nu * a.c2);
         const int64_t nch = (d.N + rg.CH - 1) / rg.CH;
         for (int64_t c = 0; c < nch; ++c) T.push_back(make_int2(j, (int)c));
-        lds = std::max(lds, step1d_lds_bytes(b->order, s, a.NT, a.D));
+        lds = std::max(lds, step1d_lds_bytes(b->order, s, a.NT, a.D, step1d_points_per_thread()));
     }
     if ((int64_t)T.size() > b->tbl_cap) return fail(AT_ERR_STATE, "batch block table overflow");
     AT_HIP(hipStreamSynchronize(b->st));
@@ -907,6 +947,7 @@ static at_status batch_layout(const at_config *cfgs, int32_t count, std::vector<
     for (int j = 0; j < count; ++j) {
         at_status st = derive(&cfgs[j], ds[j]);
         if (st) return fail(st, "instance %d: %s", j, g_err.c_str());
+        ds[j].fppt = step1d_points_per_thread();        // the batched kernel's layout
         if (cfgs[j].dim != 1) return fail(AT_ERR_ARG, "instance %d: batched form is 1D", j);
         if (cfgs[j].record) return fail(AT_ERR_ARG, "instance %d: record mode not batched", j);
         if (cfgs[j].order != cfgs[0].order || cfgs[j].adv_mode != cfgs[0].adv_mode ||

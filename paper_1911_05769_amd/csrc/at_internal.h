@@ -102,10 +102,10 @@ hipError_t launch_delays(int8_t *out, int64_t nsteps, int64_t F, int L, int m, i
                          uint64_t seed, hipStream_t st);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
-size_t step1d_lds_bytes(int order, int s, int NT, int D);
+size_t step1d_lds_bytes(int order, int s, int NT, int D, int ppt);
 int step1d_points_per_thread();
 int step1d_plain_points_per_thread();
-hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, bool fma,
+hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, bool fma, int ppt,
                          int64_t nblocks, hipStream_t st);
 hipError_t launch_step1d_batch(const Step1D *descs, const int2 *tbl, int64_t nblocks, int order,
                                bool linear, bool fma, int64_t n0, int flip, size_t lds,
@@ -113,9 +113,8 @@ hipError_t launch_step1d_batch(const Step1D *descs, const int2 *tbl, int64_t nbl
 hipError_t launch_adj1d(const Adj1D &a, int order, bool linear, int64_t nblocks,
                         hipStream_t st);
 int adj1d_points_per_block();
-hipError_t launch_adj1d_fused(const AdjF &a, int order, bool linear, int64_t nblocks, size_t lds,
-                              hipStream_t st);
-int adj1d_fused_points_per_thread();
+hipError_t launch_adj1d_fused(const AdjF &a, int order, bool linear, int ppt, int64_t nblocks,
+                              size_t lds, hipStream_t st);
 size_t adj1d_fused_lds_bytes(int order, int S, int NT, int L);
 hipError_t launch_gnu_final(const double *part, int64_t nparts, double *out, hipStream_t st);
 hipError_t launch_stats(const double *u, int64_t n, double *part, double *out3, hipStream_t st);

@@ -464,10 +464,10 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     }
 }
 
-template <int ORDER, bool LINEAR, bool FMA>
+template <int ORDER, bool LINEAR, bool FMA, int PPT>
 __global__ __launch_bounds__(kThreads) void k_step1d_aligned(Step1D a)
 {
-    step1d_aligned_body<ORDER, LINEAR, FMA>(a, blockIdx.x);
+    step1d_aligned_body<ORDER, LINEAR, FMA, true, PPT>(a, blockIdx.x);
 }
 
 // one step per launch (the plain form): 8 points per thread, a smaller
@@ -643,41 +643,57 @@ int grid_for(int64_t n)
 int step1d_points_per_thread() { return kPPT; }
 int step1d_plain_points_per_thread() { return kPPTPlain; }
 
-size_t step1d_lds_bytes(int order, int s, int NT, int D)
+size_t step1d_lds_bytes(int order, int s, int NT, int D, int ppt)
 {
     const int H = order / 2;
-    const size_t stage = (size_t)kThreads * kPPT + kThreads;
+    const size_t stage = (size_t)kThreads * ppt + kThreads;
     // exchange buffers, edge history of D + s - 1 levels, delays (bytes)
     const size_t steps = (size_t)2 * kThreads * 2 * H + (size_t)(D + s - 1) * NT * 2 * H +
                          ((size_t)s * NT * 2 + 7) / 8;
     return 8 * (stage > steps ? stage : steps);
 }
 
-hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, bool fma,
+hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, bool fma, int ppt,
                          int64_t nblocks, hipStream_t st)
 {
-    size_t lds = step1d_lds_bytes(order, a.s, a.NT, a.D);
-    if (aligned && a.s == 1) {
+    const bool plain = aligned && a.s == 1 && ppt == kPPTPlain;
+    size_t lds = step1d_lds_bytes(order, a.s, a.NT, a.D, aligned ? ppt : kPPT);
+    if (plain) {
         const size_t stage = (size_t)kThreads * kPPTPlain + kThreads;
         const size_t xch = (size_t)2 * kThreads * order;
         lds = 8 * (stage > xch ? stage : xch);
     }
     dim3 grid((unsigned)nblocks), block(kThreads);
 #define AT_L(K, O, LI, F) hipLaunchKernelGGL((K<O, LI, F>), grid, block, lds, st, a)
-#define AT_DISPATCH(K)                                                                   \
+#define AT_LP(O, LI, F, P) hipLaunchKernelGGL((k_step1d_aligned<O, LI, F, P>), grid, block, lds, st, a)
+#define AT_DISPATCH(L3)                                                                  \
     do {                                                                                 \
         if (order == 2) {                                                                \
-            if (linear) { if (fma) AT_L(K, 2, true, true); else AT_L(K, 2, true, false); } \
-            else { if (fma) AT_L(K, 2, false, true); else AT_L(K, 2, false, false); }       \
+            if (linear) { if (fma) L3(2, true, true); else L3(2, true, false); }         \
+            else { if (fma) L3(2, false, true); else L3(2, false, false); }              \
         } else {                                                                         \
-            if (linear) { if (fma) AT_L(K, 4, true, true); else AT_L(K, 4, true, false); } \
-            else { if (fma) AT_L(K, 4, false, true); else AT_L(K, 4, false, false); }       \
+            if (linear) { if (fma) L3(4, true, true); else L3(4, true, false); }         \
+            else { if (fma) L3(4, false, true); else L3(4, false, false); }              \
         }                                                                                \
     } while (0)
-    if (aligned && a.s == 1) AT_DISPATCH(k_step1d_plain);
-    else if (aligned) AT_DISPATCH(k_step1d_aligned);
-    else AT_DISPATCH(k_step1d);
+#define L_PLAIN(O, LI, F) AT_L(k_step1d_plain, O, LI, F)
+#define L_GEN(O, LI, F) AT_L(k_step1d, O, LI, F)
+#define L_A16(O, LI, F) AT_LP(O, LI, F, 16)
+#define L_A8(O, LI, F) AT_LP(O, LI, F, 8)
+#define L_A4(O, LI, F) AT_LP(O, LI, F, 4)
+    if (plain) AT_DISPATCH(L_PLAIN);
+    else if (!aligned) AT_DISPATCH(L_GEN);
+    else if (ppt == 16) AT_DISPATCH(L_A16);
+    else if (ppt == 8) AT_DISPATCH(L_A8);
+    else if (ppt == 4) AT_DISPATCH(L_A4);
+    else return hipErrorInvalidValue;
+#undef L_PLAIN
+#undef L_GEN
+#undef L_A16
+#undef L_A8
+#undef L_A4
 #undef AT_DISPATCH
+#undef AT_LP
 #undef AT_L
     return hipGetLastError();
 }

@@ -42,8 +42,9 @@ def stepper(gpu, N, P, order, L, nu, dt, nsteps, dist=0, seed=7, **kw):
                        dist=dist, **kw)
 
 
-def gpu_run(gpu, u0, N, P, order, L, nu, dt, nsteps, fuse=1, **kw):
+def gpu_run(gpu, u0, N, P, order, L, nu, dt, nsteps, fuse=1, variant=0, **kw):
     st = stepper(gpu, N, P, order, L, nu, dt, nsteps, **kw)
+    st.set_variant(variant)          # 1D: 0 automatic, 1/2/3: 16/8/4 points per thread
     st.set_fuse(fuse)
     u, s = dev(u0), torch.empty(N, dtype=torch.float64, device="cuda")
     st.run(u, s, nsteps)
@@ -138,13 +139,15 @@ def test_fused_equals_plain_and_oracle(gpu, case):
     plain, st = gpu_run(gpu, u0, N, P, order, L, nu, dt, nst, fuse=1, dist=dist)
     ref = oracle.run1d(u0, N, P, order, L, nu, dt, st.delays(), nst)
     assert relerr(plain, ref) <= TOL
-    for s in (2, 3, 4, 5, 8, 13, 16, 32):
-        try:
-            got, _ = gpu_run(gpu, u0, N, P, order, L, nu, dt, nst, fuse=s, dist=dist)
-        except gpu.AtError as e:
-            assert e.status == gpu.AT_ERR_ARG      # above this grid's limit
-            continue
-        assert np.array_equal(got, plain), "fuse %d differs" % s
+    for v in (0, 1, 2, 3):
+        for s in (2, 3, 4, 5, 8, 13, 16, 32):
+            try:
+                got, _ = gpu_run(gpu, u0, N, P, order, L, nu, dt, nst, fuse=s, variant=v,
+                                 dist=dist)
+            except gpu.AtError as e:
+                assert e.status == gpu.AT_ERR_ARG  # above this grid's limit / tile width
+                continue
+            assert np.array_equal(got, plain), "variant %d fuse %d differs" % (v, s)
 
 
 # ---------------------------------------------------------------- full size (2^24, order 4)
