@@ -28,6 +28,13 @@ FP64_ADDMUL_PEAK_TFLOPS = 39.3  # 256 CU x 64 FP64 lanes/clk x 2.4 GHz: one FP64
                                 # instruction per lane per clock (78.6 with every one an FMA)
 METRIC = "grid-point updates/s & % HBM peak (AT step, adjoint, batched) vs plain form"
 
+# HBM bytes per launch of the headline kernel (32 fused steps), from rocprofv3
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scales from a plain 1 GiB copy); only
+# reported while the kernel source is the one the counters were taken on.
+TRAFFIC = {"source": "paper_1911_05769_amd/csrc/at_step1d.hip",
+           "md5": "053f8835c32b4f0abc2cce94daa39df0", "fuse": 32,
+           "bytes_per_launch": (70738.8 * 2.0 + 139199.0) * 1024}
+
 
 def eprint(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -126,11 +133,25 @@ def bench_c2(args, torch, at, I, fuse=None, label="main", arith=0):
     return res
 
 
+def measured_traffic(r):
+    """Counter-measured HBM bytes per launch, or None when they do not apply."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, TRAFFIC["source"]), "rb") as f:
+            md5 = hashlib.md5(f.read()).hexdigest()
+    except OSError:
+        return None
+    if md5 != TRAFFIC["md5"] or r["s"] != TRAFFIC["fuse"] or r.get("arith", 0) != 0:
+        return None
+    return round(TRAFFIC["bytes_per_launch"])
+
+
 def roofline(r):
+    traffic = measured_traffic(r)
     hbm = dict(bound="hbm", achieved=round(r["gbps"], 2), peak=HBM_PEAK_GBPS, unit="GB/s",
-               frac=round(r["gbps"] / HBM_PEAK_GBPS, 4), traffic=None)
+               frac=round(r["gbps"] / HBM_PEAK_GBPS, 4), traffic=traffic)
     alu = dict(bound="alu", achieved=round(r["tflops"], 4), peak=round(r["alu_peak"], 2),
-               unit="TFLOP/s", frac=round(r["tflops"] / r["alu_peak"], 4), traffic=None)
+               unit="TFLOP/s", frac=round(r["tflops"] / r["alu_peak"], 4), traffic=traffic)
     return (hbm, alu) if hbm["frac"] >= alu["frac"] else (alu, hbm)
 
 
@@ -143,7 +164,8 @@ def cpu_baseline(res):
     t0 = time.perf_counter()
     oracle.run1d(wl.u0, N, P, wl.order, wl.L, wl.nu, wl.dt, k, 2)
     probe = time.perf_counter() - t0
-    steps = int(max(2, min(wl.nsteps, round(12.0 / max(probe / 2, 1e-6)))))
+    # the 2-step probe carries start-up costs: aim it at ~30 s for ~10-15 s of work
+    steps = int(max(2, min(wl.nsteps, round(30.0 / max(probe / 2, 1e-6)))))
     t0 = time.perf_counter()
     oracle.run1d(wl.u0, N, P, wl.order, wl.L, wl.nu, wl.dt, k, steps)
     el = time.perf_counter() - t0
@@ -232,7 +254,7 @@ def main():
         "config": {"workload": main_res["wl"].name, "n": main_res["wl"].n[0],
                    "p": main_res["wl"].p[0], "order": 4, "L": 4, "nsteps": 2000,
                    "fuse_steps": main_res["s"], "arith": "exact order, no contraction",
-                   "kernel": "k_step1d_aligned<4,false,false>"},
+                   "kernel": "k_step1d_aligned<4,false,false,16>"},
         "roofline": rl,
         "roofline_other": rl_other,
     }

@@ -621,13 +621,25 @@ __global__ __launch_bounds__(kThreads) void k_loss_part(const double *u, const d
     }
 }
 
-// out = sum of compensated pairs part[i*2], part[i*2+1], i in order
-__global__ void k_pairs_final(const double *part, int64_t np, double *out)
+// out = sum of the compensated pairs part[i*2], part[i*2+1] in a fixed
+// order: thread t merges pairs t, t+256, ... in turn, each wave combines its
+// lanes by the fixed shuffle tree, wave 0 the four wave sums in order
+__global__ __launch_bounds__(kThreads) void k_pairs_final(const double *part, int64_t np,
+                                                          double *out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double red[kThreads / 64][2];
+    const int t = threadIdx.x;
     Acc S{0.0, 0.0};
-    for (int64_t b = 0; b < np; ++b) acc_merge(S, Acc{part[b * 2], part[b * 2 + 1]});
-    out[0] = S.s + S.c;
+#pragma unroll 4
+    for (int64_t b = t; b < np; b += kThreads) acc_merge(S, Acc{part[b * 2], part[b * 2 + 1]});
+    S = wave_acc(S);
+    if ((t & 63) == 0) { red[t >> 6][0] = S.s; red[t >> 6][1] = S.c; }
+    __syncthreads();
+    if (t == 0) {
+        Acc T{0.0, 0.0};
+        for (int w = 0; w < kThreads / 64; ++w) acc_merge(T, Acc{red[w][0], red[w][1]});
+        out[0] = T.s + T.c;
+    }
 }
 
 int grid_for(int64_t n)
@@ -754,13 +766,13 @@ hipError_t launch_loss(const double *u, const double *t, double *lam, int64_t n,
     int nb = grid_for(n);
     if (nb > kRedBlocks) nb = kRedBlocks;
     hipLaunchKernelGGL(k_loss_part, dim3(nb), dim3(kThreads), 0, st, u, t, lam, n, part);
-    hipLaunchKernelGGL(k_pairs_final, dim3(1), dim3(64), 0, st, part, (int64_t)nb, J);
+    hipLaunchKernelGGL(k_pairs_final, dim3(1), dim3(kThreads), 0, st, part, (int64_t)nb, J);
     return hipGetLastError();
 }
 
 hipError_t launch_gnu_final(const double *part, int64_t nparts, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pairs_final, dim3(1), dim3(64), 0, st, part, nparts, out);
+    hipLaunchKernelGGL(k_pairs_final, dim3(1), dim3(kThreads), 0, st, part, nparts, out);
     return hipGetLastError();
 }
 
