@@ -393,13 +393,13 @@ def bench_adjoint(args, torch, at, I):
     u0 = torch.from_numpy(wl.u0).cuda()
     scr = torch.empty_like(u0)
     tst = at.Stepper(n=N, p=P, order=2, L=wl.L, nu=wl.extra["nu_target"], dt=wl.dt,
-                     nsteps_max=nst, seed=wl.seed, fuse_steps=8)
+                     nsteps_max=nst, seed=wl.seed, fuse_steps=32)
     target = u0.clone()
     tst.run(target, scr, nst)
     times = []
     for rep in range(max(1, args.steps)):
         st = at.Stepper(n=N, p=P, order=2, L=wl.L, nu=wl.nu, dt=wl.dt, nsteps_max=nst,
-                        seed=wl.seed, record=True, ckpt_every=C, fuse_steps=8)
+                        seed=wl.seed, record=True, ckpt_every=C, fuse_steps=32)
         u = u0.clone()
         lam = torch.empty_like(u)
         torch.cuda.synchronize()

@@ -710,7 +710,7 @@ at_status at_adjoint(at_ctx *c, const double *lambda_T, double *grad_u0, double 
             // rebuild levels a0+1 .. a1-1: fused launches that also store every
             // intermediate level (aligned layout), else one launch per step
             const bool fused = region_1d(d, 2).aligned;
-            const int sr = fused ? std::min(16, max_fuse(c)) : 1;
+            const int sr = fused ? max_fuse(c) : 1;
             for (int64_t n = a0; n + 1 < a1;) {
                 const int s = (int)std::min<int64_t>(sr, a1 - 1 - n);
                 at_status st = launch_1d(c, c->seg + (n - a0) * N, c->seg + (n + s - a0) * N, n, s,
