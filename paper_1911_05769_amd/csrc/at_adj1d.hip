@@ -210,9 +210,12 @@ __global__ __launch_bounds__(kThreads) void k_adj1d(Adj1D a)
             const int q = side == 0 ? (int)(o - (a.W - H)) : (int)o;
             // LDS index of the first (fs 0) / last (fs 1) point of tile tf
             const int ri = side == 0 ? r + (H - q) : r - (q + 1);
-            for (int dn = 0; dn < a.L + M; ++dn) {
+            // summed newest level first (the order in which the fused reverse
+            // launches accumulate them), then added to acc as one term
+            double gsum = 0.0;
+            for (int dn = a.L + M - 1; dn >= 0; --dn) {
                 const int64_t n2 = a.n + dn;
-                if (n2 >= a.nsteps_total) break;
+                if (n2 >= a.nsteps_total) continue;
                 const int kk = a.delays[n2 * F + 2 * tf + fs];
                 const int j = dn - kk;
                 const int need = (kk == 0 || stale) ? 1 : M;
@@ -221,8 +224,9 @@ __global__ __launch_bounds__(kThreads) void k_adj1d(Adj1D a)
                 if (ms >= a.Rmu) ms -= a.Rmu;
                 const double m = dn == 0 ? mu_now(fs, q, ri)
                                          : a.mu[((ms * a.P + tf) * 2 + fs) * H + q];
-                acc += hweight(kk, stale, j, M) * m;
+                gsum += hweight(kk, stale, j, M) * m;
             }
+            acc += gsum;
         }
         a.lam_out[g] = acc;
         acc_add(gacc, lam * (a.dt * D2));
@@ -278,7 +282,8 @@ __global__ __launch_bounds__(kThreads) void k_adj1d_fused(AdjF a)
     double *xch = lds;                                        // [2][2 arrays][2H][kThreads]
     double *eh = xch + 2 * 2 * NS * kThreads;                 // [LV][NT][2][H]: u edges, levels nt-S-DW ..
     double *muh = eh + (size_t)LV * NT * 2 * H;               // [LV][NT][2][H]: mu, levels nt-S ..
-    int8_t *kd = reinterpret_cast<int8_t *>(muh + (size_t)LV * NT * 2 * H);   // [LV][NT][2]: rows nt-S ..
+    double *gt = muh + (size_t)LV * NT * 2 * H;               // [S][NT][2][H]: gathered mu, levels nt-S ..
+    int8_t *kd = reinterpret_cast<int8_t *>(gt + (size_t)S * NT * 2 * H);     // [LV][NT][2]: rows nt-S ..
 
     const int tid = threadIdx.x;
     const int64_t c0 = (int64_t)blockIdx.x * a.CH;
@@ -459,23 +464,29 @@ __global__ __launch_bounds__(kThreads) void k_adj1d_fused(AdjF a)
                 const int stl = side == 0 ? tl0 + 1 : tl0 - 1;
                 const int fs = side == 0 ? 0 : 1;
                 const int q = side == 0 ? j - (PPT - H) : j;
-                for (int dn = 0; dn <= DW; ++dn) {
-                    const int64_t n2 = n + dn;
-                    if (n2 >= a.nsteps_total) break;
-                    const int r2 = krow + dn;
-                    const int kk = kd[(r2 * NT + stl) * 2 + fs];
-                    const int jw = dn - kk;
-                    const int need = (kk == 0 || stale) ? 1 : M;
-                    if (jw < 0 || jw >= need) continue;
-                    const double m = dn == 0 ? (side == 0 ? mu_lo(q) : mu_hi(q))
-                                             : muh[((r2 * NT + stl) * 2 + fs) * H + q];
-                    acc += hweight(kk, stale, jw, M) * m;
-                }
+                // later levels' contributions, accumulated newest first by their
+                // producers; then this level's own (k = 0: the raw neighbour)
+                double g = gt[((krow * NT + stl) * 2 + fs) * H + q];
+                if (kd[(krow * NT + stl) * 2 + fs] == 0)
+                    g += hweight(0, stale, 0, M) * (side == 0 ? mu_lo(q) : mu_hi(q));
+                acc += g;
             }
             res[j] = acc;
             if (owns) acc_add(gacc, lg * (a.dt * D2));
         }
-        // ---- mu^n of this tile's faces: LDS for later steps, the ring for later launches
+        // ---- mu^n of this tile's faces: added to the gathered sums of the
+        // earlier levels of this launch that it feeds (n-k-j, weight dH/dv_j),
+        // and to the ring for later launches
+        auto scatter = [&](int side, int q, double m) {
+            const int kk = kd[(krow * NT + tl0) * 2 + side];
+            const int need = (kk == 0 || stale) ? 1 : M;
+            for (int jw = 0; jw < need; ++jw) {
+                const int64_t nt2 = n - kk - jw;      // level this contribution belongs to
+                if (nt2 == n || nt2 < nlo) continue;  // own level: gathered directly
+                double &gref = gt[((((int)(nt2 - nlo)) * NT + tl0) * 2 + side) * H + q];
+                gref += hweight(kk, stale, jw, M) * m;
+            }
+        };
         if (lo_edge || hi_edge) {
             const int64_t ms = n % a.Rmu;
 #pragma unroll
@@ -485,7 +496,7 @@ __global__ __launch_bounds__(kThreads) void k_adj1d_fused(AdjF a)
 #pragma unroll
                     for (int e = 0; e < H; ++e)
                         if (e <= q) m += lam[e] * Ps(q - e, uc[e]);
-                    muh[((krow * NT + tl0) * 2 + 0) * H + q] = m;
+                    scatter(0, q, m);
                     if (owns) a.mu[((ms * a.P + tp0) * 2 + 0) * H + q] = m;
                 }
                 if (hi_edge) {                        // own last h points feed the high face
@@ -493,7 +504,7 @@ __global__ __launch_bounds__(kThreads) void k_adj1d_fused(AdjF a)
 #pragma unroll
                     for (int e = 0; e < H; ++e)
                         if (e <= H - 1 - q) m += lam[PPT - 1 - e] * Ps(H + q + e, uc[PPT - 1 - e]);
-                    muh[((krow * NT + tl0) * 2 + 1) * H + q] = m;
+                    scatter(1, q, m);
                     if (owns) a.mu[((ms * a.P + tp0) * 2 + 1) * H + q] = m;
                 }
             }
@@ -511,6 +522,31 @@ __global__ __launch_bounds__(kThreads) void k_adj1d_fused(AdjF a)
         for (int j = 0; j < PPT; ++j) ub[j] = 0.0;
     }
     __syncthreads();                          // LDS tables ready
+    // delayed contributions to the levels of this launch from mu levels
+    // written by earlier launches (nt ..), newest first; the launch's own mu
+    // levels are added by their producers as they are computed
+    {
+        const int ng = S * NT * 2 * H;
+        for (int e = tid; e < ng; e += kThreads) {
+            const int q = e % H;
+            const int side = (e / H) & 1;
+            const int tl = (e / (2 * H)) % NT;
+            const int r = (e / (2 * H)) / NT;
+            const int64_t n = nlo + r;
+            double g = 0.0;
+            int64_t top = n + DW;
+            if (top > a.nsteps_total - 1) top = a.nsteps_total - 1;
+            for (int64_t n2 = top; n2 >= a.nt && n2 > n; --n2) {
+                const int r2 = (int)(n2 - nlo);
+                const int kk = kd[(r2 * NT + tl) * 2 + side];
+                const int jw = (int)(n2 - n) - kk;
+                const int need = (kk == 0 || stale) ? 1 : M;
+                if (jw < 0 || jw >= need) continue;
+                g += hweight(kk, stale, jw, M) * muh[((r2 * NT + tl) * 2 + side) * H + q];
+            }
+            gt[e] = g;
+        }
+    }
     int t = 0;
     for (; t + 2 <= S; t += 2) {
         rstep(t, ua, ub);
@@ -560,7 +596,8 @@ size_t adj1d_fused_lds_bytes(int order, int S, int NT, int L)
 {
     const int H = order / 2, M = order == 2 ? 2 : 3;
     const size_t LV = (size_t)S + L + M - 1;
-    const size_t dbl = (size_t)2 * 2 * 2 * H * kThreads + 2 * LV * NT * 2 * H;
+    const size_t dbl = (size_t)2 * 2 * 2 * H * kThreads + 2 * LV * NT * 2 * H +
+                       (size_t)S * NT * 2 * H;
     return 8 * dbl + ((LV * NT * 2 + 7) / 8) * 8;
 }
 
