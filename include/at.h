@@ -129,7 +129,9 @@ at_status at_init(const at_config *cfg, at_ctx **out);
 void at_free(at_ctx *ctx);
 
 /* One step n -> n+1 in the one-launch-per-step form: reads u_in (level n),
- * writes u_out (level n+1), publishes level n's tile edges to the ring.
+ * writes u_out (level n+1) and the ring.  1D: the step publishes level n's
+ * tile edges.  3D: the call first copies level n's block faces from u_in to
+ * the ring, and the step publishes level n+1's (a run does the copy once).
  * u_in and u_out must not overlap.  AT_ERR_STATE past nsteps_max. */
 at_status at_step(at_ctx *ctx, const double *u_in, double *u_out);
 

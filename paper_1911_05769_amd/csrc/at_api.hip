@@ -164,7 +164,9 @@ int max_fuse_1d(const Derived &d);
 // level of the run (the adjoint re-reads them).
 int ring_levels(const at_config *c, const Derived &d)
 {
-    const int smax = d.dim == 1 ? kMaxFuse : 1;   // any points-per-thread choice
+    // 1D: any steps-per-launch and points-per-thread choice; 3D: a step reads
+    // levels n-L-1 .. n and publishes level n+1
+    const int smax = d.dim == 1 ? kMaxFuse : 2;
     int64_t R = c->L + d.m - 1 + smax;
     if (c->record) R = std::max<int64_t>(R, c->nsteps_max + 1);
     return (int)R;
@@ -313,6 +315,7 @@ at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int 
 
 // 3D launcher (at_step3d.hip)
 at_status at3_launch(at_ctx *c, const double *uin, double *uout, int64_t n0, int s, int publish);
+at_status at3_publish(at_ctx *c, const double *u, int64_t n);
 int at3_max_fuse(const at_ctx *c);
 int at3_variants();
 bool at3_variant_ok(const at_config *c, int var);
@@ -541,6 +544,10 @@ at_status at_step(at_ctx *c, const double *u_in, double *u_out)
                                                   (long long)c->n);
     if (c->cfg.record && c->n % c->cfg.ckpt_every == 0)
         AT_HIP(launch_copy(c->ckpt + (c->n / c->cfg.ckpt_every) * c->d.N, u_in, c->d.N, c->st));
+    if (c->d.dim == 3) {                      // the face values of level n, from u_in
+        const at_status sp = at3_publish(c, u_in, c->n);
+        if (sp) return sp;
+    }
     at_status st = launch_any(c, u_in, u_out, c->n, 1, 1);
     if (st) return st;
     c->n += 1;
@@ -558,6 +565,10 @@ at_status at_run(at_ctx *c, double *u, double *scratch, int64_t nsteps)
     double *cur = u, *oth = scratch;
     int64_t left = nsteps;
     const int64_t C = c->cfg.ckpt_every;
+    if (c->d.dim == 3 && nsteps > 0) {        // the face values of level n, from u
+        const at_status sp = at3_publish(c, u, c->n);
+        if (sp) return sp;
+    }
     while (left > 0) {
         int64_t s = std::min<int64_t>(c->fuse, left);
         if (c->cfg.record) {

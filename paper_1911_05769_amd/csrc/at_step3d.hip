@@ -124,7 +124,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
         }
     }
     const int8_t *krow = A.delays + A.n * A.F;
-    const int64_t slot = A.slot0;
+    const int64_t slot = A.slot0 + 1 == A.R ? 0 : A.slot0 + 1;   // level n+1 is published
 
     int bz = Z0 / A.Wz, lz = Z0 - bz * A.Wz;
     int kbz = -1, kc[6] = {0, 0, 0, 0, 0, 0};
@@ -190,6 +190,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
             }
             const double ux = zc[0], uy = zc[1], uz = zc[2];
             double *out = A.uout + (int64_t)z * plane + col;
+            double ov[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const double u = zc[c];
@@ -200,16 +201,17 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
                 const double D1z = (zh - zl) * A.c1[2], D2z = ((zh - 2.0 * u) + zl) * A.c2[2];
                 const double lap = (D2x + D2y) + D2z;
                 const double adv = (ux * D1x + uy * D1y) + uz * D1z;
-                out[c * A.npt] = u + A.dt * (A.nu * lap - adv);
+                ov[c] = u + A.dt * (A.nu * lap - adv);
+                out[c * A.npt] = ov[c];
             }
-            // publish level-n values of points on block faces
+            // publish the level-(n+1) values of points on block faces
             const bool onface = lx == 0 || lx == A.Wx - 1 || ly == 0 || ly == A.Wy - 1 ||
                                 lz == 0 || lz == A.Wz - 1;
             if (A.publish && onface) {
                 double *base = A.ring + slot * A.level + b * A.bstride;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const double u = zc[c];
+                    const double u = ov[c];
                     if (lx == 0) base[A.foff[0] + c * A.psz[0] + px] = u;
                     if (lx == A.Wx - 1) base[A.foff[1] + c * A.psz[0] + px] = u;
                     if (ly == 0) base[A.foff[2] + c * A.psz[1] + py] = u;
@@ -248,24 +250,26 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
 }
 
 
-// One neighbour value triple (3 components) for a tile rim or a z face: the
-// ring levels n-k and n-k-1 of the neighbour block's face when k > 0, else
-// the raw field value (loaded twice from the same address).  Every lane of a
-// role issues the same six loads whatever k is, so the wait counts stay
-// static and no later wait drains the planes in flight.
+// One neighbour value triple (3 components) for a tile rim or a z face.
+// Across a block face it comes from the ring: levels n-k and n-k-1 of the
+// neighbour block's face (k = 0: level n, which the previous step published
+// there, contiguous along the face); inside a block, from the field (loaded
+// twice from the same address).  Every lane of a role issues the same six
+// loads whatever k is, so the wait counts stay static and no later wait
+// drains the planes in flight.
 struct Nb3 {
     double a0, a1, a2;        // level n-k (or the field)
     double b0, b1, b2;        // level n-k-1 (or a repeat of a)
     int k;
 };
 
-__device__ __forceinline__ Nb3 load_nb3(const double *ring, const double *field, int k, bool stale,
-                                        int64_t oring0, int64_t oring1, int64_t cring,
+__device__ __forceinline__ Nb3 load_nb3(const double *ring, const double *field, bool face, int k,
+                                        bool stale, int64_t oring0, int64_t oring1, int64_t cring,
                                         int64_t ofield, int64_t cfield)
 {
-    const double *p0 = k > 0 ? ring + oring0 : field + ofield;
+    const double *p0 = face ? ring + oring0 : field + ofield;
     const double *p1 = (k > 0 && !stale) ? ring + oring1 : p0;
-    const int64_t cs = k > 0 ? cring : cfield;
+    const int64_t cs = face ? cring : cfield;
     Nb3 r;
     r.k = k;
     r.a0 = p0[0];
@@ -404,7 +408,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
             const int k = r_face ? kdl[6 * (bz - bz0) + r_fidx] : 0;
             const int64_t off = (r_blk + (int64_t)bz * PyPx) * bstride + r_foff +
                                 (int64_t)lz * r_lzmul + r_pos;
-            rr = load_nb3(A.ring, U0, k, stale, lvl(k) + off, lvl(k + 1) + off, r_cring,
+            rr = load_nb3(A.ring, U0, r_face, k, stale, lvl(k) + off, lvl(k + 1) + off, r_cring,
                           (int64_t)p * plane + r_field, npt);
         }
     };
@@ -429,7 +433,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
             const int nbz = wrap32(bz + (zside ? 1 : -1), A.Pz);
             const int64_t off = (z_blk + (int64_t)nbz * PyPx) * bstride +
                                 (zside ? zhi_foff : zlo_foff) + ly * Wx + lx;
-            zr = load_nb3(A.ring, U0, k, stale, lvl(k) + off, lvl(k + 1) + off, psz2, 0, npt);
+            zr = load_nb3(A.ring, U0, true, k, stale, lvl(k) + off, lvl(k + 1) + off, psz2, 0, npt);
         }
     };
 
@@ -453,7 +457,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
     finish_rims(0);
     take_z();
     if (Z0 + 1 < Z1) issue(Z0 + 1);
-    const int64_t slot = A.slot0;
+    const int64_t slot = A.slot0 + 1 == A.R ? 0 : A.slot0 + 1;   // level n+1 is published
     const double c10 = A.c1[0], c11 = A.c1[1], c12 = A.c1[2];
     const double c20 = A.c2[0], c21 = A.c2[1], c22 = A.c2[2];
     const double nu = A.nu, dt = A.dt;
@@ -473,6 +477,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
         __syncthreads();
         const double ux = zc0, uy = zc1, uz = zc2;
         double *out = A.uout + (int64_t)z * plane + col;
+        double ov[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double u = c == 0 ? zc0 : (c == 1 ? zc1 : zc2);
@@ -487,16 +492,17 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
             const double D1z = (zh - zl) * c12, D2z = ((zh - 2.0 * u) + zl) * c22;
             const double lap = (D2x + D2y) + D2z;
             const double adv = (ux * D1x + uy * D1y) + uz * D1z;
-            out[c * npt] = u + dt * (nu * lap - adv);
+            ov[c] = u + dt * (nu * lap - adv);
+            out[c * npt] = ov[c];
         }
-        // publish level-n values of points on block faces
+        // publish the level-(n+1) values of points on block faces
         if (A.publish && (lx == 0 || lx == Wx - 1 || ly == 0 || ly == Wy - 1 || lz == 0 ||
                           lz == Wz - 1)) {
             double *base = A.ring + slot * level + (((int64_t)bz * Py + by) * Px + bx) * bstride;
             const int px = lz * Wy + ly, py = lz * Wx + lx, pz = ly * Wx + lx;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double u = c == 0 ? zc0 : (c == 1 ? zc1 : zc2);
+                const double u = ov[c];
                 if (lx == 0) base[A.foff[0] + c * psz0 + px] = u;
                 if (lx == Wx - 1) base[A.foff[1] + c * psz0 + px] = u;
                 if (ly == 0) base[A.foff[2] + c * psz1 + py] = u;
@@ -567,7 +573,7 @@ __global__ __launch_bounds__(TX * TY) void k_step3d_direct(Step3D A)
         zp[c] = U(c, wrap32(Z0 + 1, nz) * plane + col);
     }
     const int8_t *krow = A.delays + A.n * A.F;
-    const int64_t slot = A.slot0;
+    const int64_t slot = A.slot0 + 1 == A.R ? 0 : A.slot0 + 1;   // level n+1 is published
     int bz = Z0 / A.Wz, lz = Z0 - bz * A.Wz;
     int kbz = -1, kc[6] = {0, 0, 0, 0, 0, 0};
     for (int z = Z0; z < Z1; ++z, ++lz) {
@@ -625,6 +631,7 @@ __global__ __launch_bounds__(TX * TY) void k_step3d_direct(Step3D A)
         }
         const double ux = zc[0], uy = zc[1], uz = zc[2];
         double *out = A.uout + (int64_t)po + col;
+        double ov[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double u = zc[c];
@@ -635,14 +642,15 @@ __global__ __launch_bounds__(TX * TY) void k_step3d_direct(Step3D A)
             const double D1z = (zh - zl) * A.c1[2], D2z = ((zh - 2.0 * u) + zl) * A.c2[2];
             const double lap = (D2x + D2y) + D2z;
             const double adv = (ux * D1x + uy * D1y) + uz * D1z;
-            out[c * A.npt] = u + A.dt * (A.nu * lap - adv);
+            ov[c] = u + A.dt * (A.nu * lap - adv);
+            out[c * A.npt] = ov[c];
         }
         if (A.publish && (lx == 0 || lx == A.Wx - 1 || ly == 0 || ly == A.Wy - 1 || lz == 0 ||
                           lz == A.Wz - 1)) {
             double *base = A.ring + slot * A.level + b * A.bstride;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double u = zc[c];
+                const double u = ov[c];
                 if (lx == 0) base[A.foff[0] + c * A.psz[0] + px] = u;
                 if (lx == A.Wx - 1) base[A.foff[1] + c * A.psz[0] + px] = u;
                 if (ly == 0) base[A.foff[2] + c * A.psz[1] + py] = u;
@@ -653,6 +661,34 @@ __global__ __launch_bounds__(TX * TY) void k_step3d_direct(Step3D A)
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) { zm[c] = zc[c]; zc[c] = zp[c]; zp[c] = zq[c]; }
+    }
+}
+
+// Level n's block-face values from the field into ring slot n mod R (the
+// steps read the faces of the current level from the ring; a run starts by
+// publishing them once)
+__global__ __launch_bounds__(256) void k3_publish(Step3D A)
+{
+    const int64_t nlev = A.level;
+    const int64_t slot = A.slot0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nlev;
+         e += (int64_t)gridDim.x * 256) {
+        const int64_t b = e / A.bstride;
+        const int64_t rem = e - b * A.bstride;
+        int f = 5;
+        while (f > 0 && rem < A.foff[f]) --f;
+        const int ax = f >> 1;
+        const int64_t r2 = rem - A.foff[f];
+        const int c = (int)(r2 / A.psz[ax]);
+        const int64_t pos = r2 - c * A.psz[ax];
+        const int bx = (int)(b % A.Px), by = (int)((b / A.Px) % A.Py), bz = (int)(b / (A.Px * A.Py));
+        int lx, ly, lz;
+        if (ax == 0) { lz = (int)(pos / A.Wy); ly = (int)(pos - (int64_t)lz * A.Wy); lx = (f & 1) ? A.Wx - 1 : 0; }
+        else if (ax == 1) { lz = (int)(pos / A.Wx); lx = (int)(pos - (int64_t)lz * A.Wx); ly = (f & 1) ? A.Wy - 1 : 0; }
+        else { ly = (int)(pos / A.Wx); lx = (int)(pos - (int64_t)ly * A.Wx); lz = (f & 1) ? A.Wz - 1 : 0; }
+        const int64_t x = (int64_t)bx * A.Wx + lx, y = (int64_t)by * A.Wy + ly,
+                      z = (int64_t)bz * A.Wz + lz;
+        A.ring[slot * nlev + e] = A.uin[c * A.npt + (z * A.ny + y) * A.nx + x];
     }
 }
 
@@ -710,11 +746,10 @@ bool at3_variant_ok(const at_config *c, int var)
     return Wx % TX == 0 && Wy % k3_rows(var) == 0;
 }
 
-at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, int s, int publish)
+static void fill_step3d(at_ctx *ctx, const double *uin, double *uout, int64_t n0, int publish,
+                        Step3D &A)
 {
-    if (s != 1) return at_fail(AT_ERR_ARG, "3D stepper advances one step per launch");
     const at_config *c = at_ctx_cfg(ctx);
-    Step3D A;
     A.uin = uin;
     A.uout = uout;
     A.ring = at_ctx_ring(ctx);
@@ -742,7 +777,28 @@ at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, i
     A.publish = publish;
     A.nu = c->nu;
     A.dt = c->dt;
+    A.ZC = 0;
+    A.pad0 = 0;
     at_ctx_coefs(ctx, A.c1, A.c2);
+}
+
+at_status at3_publish(at_ctx *ctx, const double *u, int64_t n)
+{
+    Step3D A;
+    fill_step3d(ctx, u, nullptr, n, 1, A);
+    int64_t g = (A.level + 255) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k3_publish, dim3((unsigned)g), dim3(256), 0, at_ctx_stream(ctx), A);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return at_fail(AT_ERR_HIP, hipGetErrorString(e));
+    return AT_OK;
+}
+
+at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, int s, int publish)
+{
+    if (s != 1) return at_fail(AT_ERR_ARG, "3D stepper advances one step per launch");
+    Step3D A;
+    fill_step3d(ctx, uin, uout, n0, publish, A);
     const int var = at_ctx_variant(ctx);
     const int TYv = k3_rows(var);
     const int64_t gx = (A.nx + TX - 1) / TX, gy = (A.ny + TYv - 1) / TYv;
