@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define AT_ABI_VERSION 1
+#define AT_ABI_VERSION 2
 
 typedef enum {
     AT_OK = 0,

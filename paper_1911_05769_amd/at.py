@@ -18,7 +18,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libat.so")
 
-AT_ABI_VERSION = 1
+AT_ABI_VERSION = 2
 AT_OK, AT_ERR_ARG, AT_ERR_SHAPE, AT_ERR_DELAY, AT_ERR_HIP, AT_ERR_NOMEM, AT_ERR_STATE = \
     0, -1, -2, -3, -4, -5, -6
 DELAY_GENERATE, DELAY_HOST = 0, 1
