@@ -42,11 +42,12 @@ def eprint(*a):
 
 def flops_per_update(order, arith=0):
     """(FP64 flops, FP64 VALU instructions) of one interior update.  Exact
-    order, no contraction: every operation is one instruction (order 2: 11,
-    order 4: 17).  Contracted mode (an FMA is two flops in one instruction):
-    order 2: 9 flops in 6 instructions, order 4: 15 flops in 10."""
+    order: order 2 has 11 flops, order 4 17; the exact scalings by 2, 8 and 16
+    share an fma with the next add (one rounding either way), so they take
+    10 and 15 instructions.  Contracted mode (an FMA is two flops in one
+    instruction): order 2: 9 flops in 6 instructions, order 4: 15 in 10."""
     if arith == 0:
-        return (11, 11) if order == 2 else (17, 17)
+        return (11, 10) if order == 2 else (17, 15)
     return (9, 6) if order == 2 else (15, 10)
 
 

@@ -87,15 +87,20 @@ __device__ __forceinline__ double update(const double *nb, double u, const Step1
         const double adv = LINEAR ? a.cadv : u;
         return fma(a.A2, T2, fma(-(adv * a.A1), T1, u));
     }
+    // Exact order: D1 = (8(r1-l1) - (r2-l2))*c1, D2 = ((16(r1+l1) - 30u) - (r2+l2))*c2
+    // (order 2: D1 = (r1-l1)*c1, D2 = ((r1 - 2u) + l1)*c2), each operation rounded
+    // on its own.  A product by 2, 8 or 16 is exact, so fusing it with the
+    // following add into one fma rounds once where the separate pair also
+    // rounds once: the same bits in one instruction instead of two.
     double D1, D2;
     if constexpr (ORDER == 2) {
         const double l1 = nb[0], r1 = nb[1];
         D1 = (r1 - l1) * a.c1;
-        D2 = ((r1 - 2.0 * u) + l1) * a.c2;
+        D2 = (fma(-2.0, u, r1) + l1) * a.c2;
     } else {
         const double l2 = nb[0], l1 = nb[1], r1 = nb[2], r2 = nb[3];
-        D1 = (8.0 * (r1 - l1) - (r2 - l2)) * a.c1;
-        D2 = ((16.0 * (r1 + l1) - 30.0 * u) - (r2 + l2)) * a.c2;
+        D1 = fma(8.0, r1 - l1, -(r2 - l2)) * a.c1;
+        D2 = (fma(16.0, r1 + l1, -(30.0 * u)) - (r2 + l2)) * a.c2;
     }
     const double adv = LINEAR ? a.cadv : u;
     const double F = a.nu * D2 - adv * D1;

@@ -115,6 +115,8 @@ def test_parity_plain(gpu, case):
     err = relerr(got, ref)
     log("  rel err %.3e bitwise %s" % (err, np.array_equal(got, ref)))
     assert err <= TOL
+    # exact-order mode: the same operations in the same order as the oracle
+    assert np.array_equal(got, ref)
     assert np.all(np.isfinite(got))
 
 
@@ -139,6 +141,7 @@ def test_fused_equals_plain_and_oracle(gpu, case):
     plain, st = gpu_run(gpu, u0, N, P, order, L, nu, dt, nst, fuse=1, dist=dist)
     ref = oracle.run1d(u0, N, P, order, L, nu, dt, st.delays(), nst)
     assert relerr(plain, ref) <= TOL
+    assert np.array_equal(plain, ref)
     for v in (0, 1, 2, 3):
         for s in (2, 3, 4, 5, 8, 13, 16, 32):
             try:
