@@ -229,7 +229,7 @@ at_status at_set_fuse(at_ctx *ctx, int32_t fuse_steps);
 
 /* Reverse steps per launch of at_adjoint.  0 (default): as many as the grid
  * allows (fused reverse launches need a tile width that is a multiple of 4,
- * else one step per launch); 1: one reverse step per launch; 2..32: at most
+ * else one step per launch); 1: one reverse step per launch; 2..64: at most
  * that many per launch (AT_ERR_ARG beyond this grid's limit).  Every setting
  * gives the same lambda bits; dJ/dnu is summed in a different grouping. */
 at_status at_set_adjoint_fuse(at_ctx *ctx, int32_t steps);

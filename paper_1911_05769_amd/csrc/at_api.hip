@@ -598,7 +598,7 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
     // 1D: steps per launch; 3D: kernel variant (one step per launch)
     std::vector<int> cands;
     if (c->d.dim == 1) {
-        for (int s : {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32})
+        for (int s : {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 56, 64})
             if (s <= mf) cands.push_back(s);
     } else {
         for (int v = 0; v < at3_variants(); ++v)

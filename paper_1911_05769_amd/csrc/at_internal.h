@@ -8,7 +8,7 @@
 namespace atk {
 
 constexpr int kThreads = 256;     // workgroup size of every stencil kernel (4 wave64)
-constexpr int kMaxFuse = 32;      // largest steps-per-launch the ring is sized for
+constexpr int kMaxFuse = 64;      // largest steps-per-launch the ring is sized for
 constexpr int kRedBlocks = 1024;  // workgroups of the first reduction pass
 
 // Arguments of one launch of the 1D stepper: s steps n0 .. n0+s-1.

@@ -51,7 +51,7 @@ def _ws(**kw):
     (dict(nu=-1.0), at.AT_ERR_ARG),
     (dict(dt=0.0), at.AT_ERR_ARG),
     (dict(dt=float("nan")), at.AT_ERR_ARG),
-    (dict(fuse_steps=33), at.AT_ERR_ARG),
+    (dict(fuse_steps=65), at.AT_ERR_ARG),
     (dict(record=True, ckpt_every=0), at.AT_ERR_ARG),
     (dict(dim=3, n=(16, 16, 16), p=(2, 2, 2), order=4), at.AT_ERR_ARG),
     (dict(adv_mode=2), at.AT_ERR_ARG),

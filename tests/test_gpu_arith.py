@@ -80,7 +80,7 @@ def test_contracted_parity_and_fused_bits(gpu, case):
     assert err <= TOL
     exact, _ = run(gpu, u0, N, P, order, L, nu, dt, nst, arith=0, dist=dist, **extra)
     assert np.array_equal(exact, ref)                 # mode 0 untouched
-    for s in (2, 3, 8, 16, 32):
+    for s in (2, 3, 8, 16, 32, 48, 64):
         try:
             got, _ = run(gpu, u0, N, P, order, L, nu, dt, nst, fuse=s, dist=dist, **extra)
         except gpu.AtError as e:

@@ -143,7 +143,7 @@ def test_fused_equals_plain_and_oracle(gpu, case):
     assert relerr(plain, ref) <= TOL
     assert np.array_equal(plain, ref)
     for v in (0, 1, 2, 3):
-        for s in (2, 3, 4, 5, 8, 13, 16, 32):
+        for s in (2, 3, 4, 5, 8, 13, 16, 32, 48, 64):
             try:
                 got, _ = gpu_run(gpu, u0, N, P, order, L, nu, dt, nst, fuse=s, variant=v,
                                  dist=dist)
