@@ -28,12 +28,12 @@ FP64_ADDMUL_PEAK_TFLOPS = 39.3  # 256 CU x 64 FP64 lanes/clk x 2.4 GHz: one FP64
                                 # instruction per lane per clock (78.6 with every one an FMA)
 METRIC = "grid-point updates/s & % HBM peak (AT step, adjoint, batched) vs plain form"
 
-# HBM bytes per launch of the headline kernel (32 fused steps), from rocprofv3
+# HBM bytes per launch of the headline kernel (56 fused steps), from rocprofv3
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scales from a plain 1 GiB copy); only
 # reported while the kernel source is the one the counters were taken on.
 TRAFFIC = {"source": "paper_1911_05769_amd/csrc/at_step1d.hip",
-           "md5": "c837ef4b4d965457760c0f32934972bc", "fuse": 32,
-           "bytes_per_launch": (70733.1 * 2.0 + 139199.0) * 1024}
+           "md5": "c837ef4b4d965457760c0f32934972bc", "fuse": 56,
+           "bytes_per_launch": (73179.0 * 2.0 + 145294.0) * 1024}
 
 
 def eprint(*a):
