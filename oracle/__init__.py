@@ -47,6 +47,8 @@ def lib():
         L.or_adjoint1d.argtypes = [_i64, _i64, _int, _int, _int, _int, _dbl, _dbl, _dbl, _dbl,
                                    _p, _i64, _p, _p, _p, _p]
         L.or_run3d.argtypes = [_p, _p, _int, _int, _dbl, _dbl, _dbl, _p, _i64, _p, _p]
+        L.or_run3ds.argtypes = [_p, _p, _int, _p, _int, _int, _dbl, _dbl, _dbl, _p, _i64, _p,
+                                _p]
         L.or_stats.argtypes = [_i64, _p, _p]
         L.or_stats.restype = None
         L.or_loss.argtypes = [_i64, _p, _p, _p]
@@ -124,17 +126,29 @@ def adjoint1d(u0, lamT, N, P, order, L, nu, dt, k, nsteps, length=2 * np.pi, sta
     return lam0, float(gnu[0])
 
 
-def run3d(u0, n, p, L, nu, dt, k, nsteps, length=2 * np.pi, stale=False) -> np.ndarray:
-    """u0: [3][nz][ny][nx]; n, p: (x, y, z) sizes and block counts."""
+def run3d(u0, n, p, L, nu, dt, k, nsteps, length=2 * np.pi, stale=False,
+          alpha=()) -> np.ndarray:
+    """u0: [3 + len(alpha)][nz][ny][nx]; n, p: (x, y, z) sizes and block counts.
+
+    Components 0..2 are the velocity (diffusivity nu); each further component
+    is a passive scalar advected by it with diffusivity alpha[s] (section 3.1,
+    Eq. (4)).
+    """
     u0 = np.ascontiguousarray(u0, dtype=np.float64)
     k = np.ascontiguousarray(k, dtype=np.int8)
     nx = np.asarray(n, dtype=np.int64)
     px = np.asarray(p, dtype=np.int64)
-    assert u0.shape == (3, n[2], n[1], n[0])
+    al = np.ascontiguousarray(alpha, dtype=np.float64).reshape(-1)
+    assert u0.shape == (3 + al.size, n[2], n[1], n[0])
     out = np.empty_like(u0)
-    st = lib().or_run3d(_ptr(nx), _ptr(px), L, 1 if stale else 0, nu, dt, length, _ptr(k),
-                        nsteps, _ptr(u0), _ptr(out))
-    _check(st, "or_run3d")
+    if al.size == 0:
+        st = lib().or_run3d(_ptr(nx), _ptr(px), L, 1 if stale else 0, nu, dt, length, _ptr(k),
+                            nsteps, _ptr(u0), _ptr(out))
+        _check(st, "or_run3d")
+    else:
+        st = lib().or_run3ds(_ptr(nx), _ptr(px), al.size, _ptr(al), L, 1 if stale else 0, nu,
+                             dt, length, _ptr(k), nsteps, _ptr(u0), _ptr(out))
+        _check(st, "or_run3ds")
     return out
 
 

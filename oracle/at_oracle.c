@@ -28,7 +28,8 @@
  *   * Standard central differences at interior points, forward Euler in time
  *     (section 3.2), for viscous Burgers u_t + u u_x = nu u_xx in 1D and the
  *     3D vector form u_i,t + u_j d_j u_i = nu d_j d_j u_i (section 3.1,
- *     Eq. (4)), periodic domain.
+ *     Eq. (4)), periodic domain, optionally with passive scalars
+ *     phi_t + u_j d_j phi = alpha d_j d_j phi (the second line of Eq. (4)).
  *   * The paper's verification problem, linear advection-diffusion
  *     u_t + c u_x = nu u_xx (section 3.2), and the "standard scheme on
  *     delayed data" configuration (halo = stale level n-k, no extrapolation)
@@ -51,6 +52,7 @@
 #define OR_ERR_SHAPE -2
 #define OR_ERR_DELAY -3
 #define OR_ERR_NOMEM -5
+#define OR_MAX_SCALARS 4
 
 /* ------------------------------------------------------------------------ */
 /* Delays                                                                    */
@@ -383,13 +385,18 @@ int or_adjoint1d(int64_t N, int64_t P, int order, int L, int halo_mode, int adv_
 }
 
 /* ------------------------------------------------------------------------ */
-/* 3D vector stepper (order 2, 7-point stencil per axis)                     */
+/* 3D vector stepper (order 2, 7-point stencil per axis), with passive        */
+/* scalars phi_k: phi_t + u_j d_j phi = alpha_k d_j d_j phi (section 3.1, the  */
+/* second line of Eq. (4)); a scalar is one more component that the velocity   */
+/* advects, with its own diffusivity                                           */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
     int64_t n[3], P[3], W[3], npt;
     int L, m, halo_mode;
+    int nc;                   /* components: 3 velocity + passive scalars */
     double nu, dt;
+    double kappa[3 + OR_MAX_SCALARS];   /* diffusivity per component (nu, then alpha_k) */
     or_coef c[3];
 } or_p3;
 
@@ -424,8 +431,8 @@ static void or_step3d(const or_p3 *p, double *const *hist, int64_t nh, const int
                 int64_t x[3] = {xx, yy, z};
                 int64_t at = (z * p->n[1] + yy) * p->n[0] + xx;
                 double vel[3] = {un[at], un[p->npt + at], un[2 * p->npt + at]};
-                for (int comp = 0; comp < 3; ++comp) {
-                    double u = vel[comp];
+                for (int comp = 0; comp < p->nc; ++comp) {
+                    double u = un[(int64_t)comp * p->npt + at];
                     double D1[3], D2[3];
                     for (int a = 0; a < 3; ++a) {
                         double l1 = or_nb3d(p, hist, nh, krow, n, comp, x, a, -1);
@@ -435,7 +442,7 @@ static void or_step3d(const or_p3 *p, double *const *hist, int64_t nh, const int
                     }
                     double lap = (D2[0] + D2[1]) + D2[2];
                     double adv = (vel[0] * D1[0] + vel[1] * D1[1]) + vel[2] * D1[2];
-                    double F = p->nu * lap - adv;
+                    double F = p->kappa[comp] * lap - adv;
                     out[(int64_t)comp * p->npt + at] = u + p->dt * F;
                 }
             }
@@ -443,12 +450,19 @@ static void or_step3d(const or_p3 *p, double *const *hist, int64_t nh, const int
     }
 }
 
-int or_run3d(const int64_t *nxyz, const int64_t *pxyz, int L, int halo_mode,
-             double nu, double dt, double length, const int8_t *k, int64_t nsteps,
-             const double *u0, double *uT)
+int or_run3ds(const int64_t *nxyz, const int64_t *pxyz, int nscalars, const double *alpha,
+              int L, int halo_mode, double nu, double dt, double length, const int8_t *k,
+              int64_t nsteps, const double *u0, double *uT)
 {
     or_p3 p;
     if (L < 0 || L > 15 || halo_mode < 0 || halo_mode > 1) return OR_ERR_ARG;
+    if (nscalars < 0 || nscalars > OR_MAX_SCALARS || (nscalars > 0 && !alpha)) return OR_ERR_ARG;
+    p.nc = 3 + nscalars;
+    for (int c = 0; c < 3; ++c) p.kappa[c] = nu;
+    for (int c = 0; c < nscalars; ++c) {
+        if (!(alpha[c] >= 0.0)) return OR_ERR_ARG;
+        p.kappa[3 + c] = alpha[c];
+    }
     if (!(nu >= 0.0) || !(dt > 0.0) || !(length > 0.0) || nsteps < 0) return OR_ERR_ARG;
     int64_t nb = 1;
     for (int a = 0; a < 3; ++a) {
@@ -466,16 +480,23 @@ int or_run3d(const int64_t *nxyz, const int64_t *pxyz, int L, int halo_mode,
     double **hist = (double **)calloc((size_t)nh, sizeof(double *));
     if (!hist) return OR_ERR_NOMEM;
     for (int64_t q = 0; q < nh; ++q) {
-        hist[q] = (double *)malloc((size_t)(3 * p.npt) * sizeof(double));
+        hist[q] = (double *)malloc((size_t)(p.nc * p.npt) * sizeof(double));
         if (!hist[q]) { for (int64_t r = 0; r < q; ++r) free(hist[r]); free(hist); return OR_ERR_NOMEM; }
     }
-    memcpy(hist[0], u0, (size_t)(3 * p.npt) * sizeof(double));
+    memcpy(hist[0], u0, (size_t)(p.nc * p.npt) * sizeof(double));
     for (int64_t n = 0; n < nsteps; ++n)
         or_step3d(&p, hist, nh, k + n * 6 * nb, n, hist[(n + 1) % nh]);
-    memcpy(uT, hist[nsteps % nh], (size_t)(3 * p.npt) * sizeof(double));
+    memcpy(uT, hist[nsteps % nh], (size_t)(p.nc * p.npt) * sizeof(double));
     for (int64_t q = 0; q < nh; ++q) free(hist[q]);
     free(hist);
     return OR_OK;
+}
+
+int or_run3d(const int64_t *nxyz, const int64_t *pxyz, int L, int halo_mode,
+             double nu, double dt, double length, const int8_t *k, int64_t nsteps,
+             const double *u0, double *uT)
+{
+    return or_run3ds(nxyz, pxyz, 0, NULL, L, halo_mode, nu, dt, length, k, nsteps, u0, uT);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -101,9 +101,12 @@ def run1d(u0, N, P, order, L, nu, dt, k, nsteps, length=2 * np.pi, stale=False,
     return hist if return_history else hist[-1]
 
 
-def run3d(u0, n, p, L, nu, dt, k, nsteps, length=2 * np.pi, stale=False):
-    """3D vector Burgers, order 2, u0[3][z][y][x]; blocks b = (bz*Py+by)*Px+bx,
-    faces f = 6b + 2a + s."""
+def run3d(u0, n, p, L, nu, dt, k, nsteps, length=2 * np.pi, stale=False, alpha=()):
+    """3D vector Burgers, order 2, u0[3 + len(alpha)][z][y][x]; blocks
+    b = (bz*Py+by)*Px+bx, faces f = 6b + 2a + s.  Components past the velocity
+    are passive scalars with diffusivities alpha."""
+    kappa = [nu, nu, nu] + list(alpha)
+    nc = len(kappa)
     nx, ny, nz = n
     Px, Py, Pz = p
     W = (nx // Px, ny // Py, nz // Pz)
@@ -118,8 +121,8 @@ def run3d(u0, n, p, L, nu, dt, k, nsteps, length=2 * np.pi, stale=False):
     for step in range(nsteps):
         un = hist[step]
         vel = [un[0], un[1], un[2]]
-        D1 = [[None] * 3 for _ in range(3)]
-        D2 = [[None] * 3 for _ in range(3)]
+        D1 = [[None] * 3 for _ in range(nc)]
+        D2 = [[None] * 3 for _ in range(nc)]
         for a in range(3):
             lo = blk[a] * W[a]
             hi = lo + W[a]
@@ -131,7 +134,7 @@ def run3d(u0, n, p, L, nu, dt, k, nsteps, length=2 * np.pi, stale=False):
                 sc = [c.copy() for c in coords]
                 sc[a] = np.mod(j, sizes[a])
                 kk = np.where(inside, 0, k[step][face]).astype(np.int64)
-                for comp in range(3):
+                for comp in range(nc):
                     v = un[comp][sc[2], sc[1], sc[0]]
                     delayed = kk > 0
                     if np.any(delayed):
@@ -151,9 +154,9 @@ def run3d(u0, n, p, L, nu, dt, k, nsteps, length=2 * np.pi, stale=False):
                         D1[comp][a] = (r1 - l1) * cs[a][0]
                         D2[comp][a] = ((r1 - 2.0 * u) + l1) * cs[a][1]
         out = np.empty_like(un)
-        for comp in range(3):
+        for comp in range(nc):
             lap = (D2[comp][0] + D2[comp][1]) + D2[comp][2]
             adv = (vel[0] * D1[comp][0] + vel[1] * D1[comp][1]) + vel[2] * D1[comp][2]
-            out[comp] = un[comp] + dt * (nu * lap - adv)
+            out[comp] = un[comp] + dt * (kappa[comp] * lap - adv)
         hist.append(out)
     return hist[-1]

@@ -14,7 +14,12 @@ dataset. The fields below are seeded stand-ins of that kind:
 * ``u0_powerlaw``   random-phase Fourier field with amplitude spectrum
                     kappa**-2 up to a cut-off wavenumber (1D);
 * ``u0_solenoidal`` divergence-free random vector field with energy spectrum
-                    kappa**(-5/3) up to a cut-off, normalised to max |u_i| = 1.
+                    kappa**(-5/3) up to a cut-off, normalised to max |u_i| = 1;
+* ``phi0_spectral`` random-phase scalar fields with spectrum kappa**(-5/3),
+                    normalised to max |phi| = 1 (the passive scalars of the
+                    second line of Eq. (4); the paper gives neither their
+                    number nor their diffusivities, so the workload fixes two
+                    scalars at Schmidt numbers nu/alpha = 1 and 2).
 
 The time step follows the rule dt = 0.2 * min(dx / max|u0|, dx^2 / (2 nu))
 (advective and diffusive limits of forward Euler, section 3.2); it is
@@ -101,6 +106,31 @@ def u0_solenoidal(n: int, kmax: int, seed: int) -> np.ndarray:
         out[comp] = np.fft.irfftn(spec, s=(n, n, n), axes=(0, 1, 2))
         del spec
     out /= np.max(np.abs(out))
+    return np.ascontiguousarray(out)
+
+
+def phi0_spectral(n: int, count: int, kmax: int, seed: int) -> np.ndarray:
+    """count scalar fields phi[count][z][y][x] on an n^3 periodic grid: complex
+    Gaussian coefficients on the shell 1 <= |kappa| <= kmax with amplitude
+    |kappa|**(-11/6), made real by an inverse real FFT, each scaled to
+    max |phi| = 1."""
+    g = rng(seed)
+    kfull = np.fft.fftfreq(n, d=1.0 / n)
+    sel = np.nonzero(np.abs(kfull) <= kmax)[0]
+    selx = np.arange(0, min(kmax, n // 2) + 1)
+    KZ, KY, KX = np.meshgrid(kfull[sel], kfull[sel], selx.astype(np.float64),
+                             indexing="ij")
+    kmag = np.sqrt(KX ** 2 + KY ** 2 + KZ ** 2)
+    shell = (kmag >= 1.0) & (kmag <= kmax)
+    amp = np.where(shell, np.where(kmag > 0, kmag, 1.0) ** (-11.0 / 6.0), 0.0)
+    out = np.empty((count, n, n, n), dtype=np.float64)
+    for s_ in range(count):
+        c = (g.standard_normal(KX.shape) + 1j * g.standard_normal(KX.shape)) * amp
+        spec = np.zeros((n, n, n // 2 + 1), dtype=np.complex128)
+        spec[np.ix_(sel, sel, selx)] = c
+        out[s_] = np.fft.irfftn(spec, s=(n, n, n), axes=(0, 1, 2))
+        del spec
+        out[s_] /= max(np.max(np.abs(out[s_])), 1e-300)
     return np.ascontiguousarray(out)
 
 
@@ -192,6 +222,25 @@ def wl_solenoidal_3d(n=512, p=8, L=3, nu=5e-3, nsteps=200, seed=BASE_SEED,
     dt = dt_rule(dx, float(np.max(np.abs(u0))), nu)
     return Workload("burgers3d_solenoidal_n%d_p%d_o2_L%d" % (n, p, L), 3, (n, n, n),
                     (p, p, p), 2, L, dist, seed, nu, dt, nsteps, u0)
+
+
+def wl_scalars_3d(n=512, p=8, L=3, nu=5e-3, schmidt=(1.0, 2.0), nsteps=200,
+                  seed=BASE_SEED, dist=DIST_UNIFORM, kmax=32) -> Workload:
+    """3D vector Burgers plus passive scalars (section 3.1, Eq. (4)): the
+    solenoidal velocity of wl_solenoidal_3d and len(schmidt) kappa^-5/3
+    scalar fields with diffusivities alpha_k = nu / Sc_k; u0 holds
+    [3 + len(schmidt)][z][y][x] and extra["alpha"] the diffusivities."""
+    km = min(kmax, n // 2 - 1)
+    vel = u0_solenoidal(n, km, seed)
+    phi = phi0_spectral(n, len(schmidt), km, seed + 1)
+    u0 = np.ascontiguousarray(np.concatenate([vel, phi], axis=0))
+    del vel, phi
+    alpha = tuple(nu / sc for sc in schmidt)
+    dx = TWO_PI / n
+    dt = dt_rule(dx, 1.0, max((nu,) + alpha))
+    return Workload("burgers3d_scalars%d_n%d_p%d_o2_L%d" % (len(schmidt), n, p, L), 3,
+                    (n, n, n), (p, p, p), 2, L, dist, seed, nu, dt, nsteps, u0,
+                    extra={"alpha": alpha})
 
 
 def wl_adjoint_1d(n=1 << 20, p=1024, L=3, nu=2e-3, nu_target=3e-3, nsteps=4000,

@@ -7,6 +7,9 @@
   a0 > sum |b_j|, is periodic on [0, 2 pi)^d.
 * Linear advection-diffusion u_t + c u_x = nu u_xx (the paper's verification
   problem, section 3.2): u = sum_j A_j exp(-nu kappa_j^2 t) sin(kappa_j (x - c t) + theta_j).
+* Passive scalar in a uniform velocity U (the second line of Eq. (4); U is an
+  exact steady solution of the velocity equation):
+  phi = sum_j A_j exp(-alpha |kappa_j|^2 t) sin(kappa_j . (x - U t) + theta_j).
 """
 import numpy as np
 
@@ -66,4 +69,21 @@ class AdvDiff1D:
         out = 0 * x
         for k, A, th in self.modes:
             out = out + A * np.exp(-self.nu * k * k * t) * np.sin(k * (x - self.c * t) + th)
+        return out
+
+
+class ScalarUniform3D:
+    def __init__(self, alpha, U, modes=(((1, 0, 0), 0.5, 0.3), ((0, 2, 0), 0.3, 1.1),
+                                        ((0, 0, 1), 0.4, 2.0), ((1, -1, 1), 0.2, 0.7))):
+        self.alpha, self.U, self.modes = alpha, U, modes
+
+    def phi(self, n, t, length=2 * np.pi):
+        x = np.arange(n) * (length / n)
+        Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+        out = 0 * X
+        for kv, A, th in self.modes:
+            kk = kv[0] ** 2 + kv[1] ** 2 + kv[2] ** 2
+            arg = (kv[0] * (X - self.U[0] * t) + kv[1] * (Y - self.U[1] * t) +
+                   kv[2] * (Z - self.U[2] * t) + th)
+            out = out + A * np.exp(-self.alpha * kk * t) * np.sin(arg)
         return out

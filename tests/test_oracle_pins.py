@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import oracle.twin as twin
-from exact import AdvDiff1D, ColeHopf1D, ColeHopf3D
+from exact import AdvDiff1D, ColeHopf1D, ColeHopf3D, ScalarUniform3D
 from paper_1911_05769_amd import inputs as I
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -392,6 +392,74 @@ def test_3d_convergence_cole_hopf():
         res[mode] = math.log2(errs[0] / errs[1])
     assert abs(res["sync"] - 2.0) < 0.1, res
     assert abs(res["at"] - 2.0) < 0.1, res
+
+
+# --------------------------------------------------------------------------
+# passive scalars (section 3.1, second line of Eq. (4))
+# --------------------------------------------------------------------------
+
+def test_scalar_copy_of_velocity_component_tracks_it():
+    """phi0 = u_c with alpha = nu obeys the same equation as u_c: it must stay
+    bitwise equal to it under any delays, for each c; the velocity must not
+    see the scalars."""
+    n, p, L, nst, nu = (8, 6, 10), (2, 3, 2), 3, 25, 0.05
+    u0 = I.u0_modes3d(n, 4, 2, 7)
+    k = oracle.delays(nst, 6 * 12, L, 2, 0, 9)
+    ref = oracle.run3d(u0, n, p, L, nu, 0.01, k, nst)
+    s0 = np.concatenate([u0, u0[[2, 0, 1]]], axis=0)
+    out = oracle.run3d(s0, n, p, L, nu, 0.01, k, nst, alpha=(nu, nu, nu))
+    assert np.array_equal(out[:3], ref)
+    assert np.array_equal(out[3:], ref[[2, 0, 1]])
+
+
+def test_scalar_alpha_zero_constant_and_stale():
+    n, p, nst = (6, 8, 4), (3, 2, 2), 20
+    u0 = I.u0_modes3d(n, 3, 2, 4)
+    s0 = np.concatenate([u0, np.full((1,) + u0.shape[1:], -0.625)], axis=0)
+    for stale in (False, True):
+        k = oracle.delays(nst, 6 * 12, 4, 2, 1, 5)
+        out = oracle.run3d(s0, n, p, 4, 0.05, 0.01, k, nst, alpha=(0.0,), stale=stale)
+        assert np.all(out[3] == -0.625)
+
+
+def test_bruteforce_equals_oracle_3d_scalars():
+    n, p = (8, 6, 4), (2, 3, 2)
+    g = np.random.default_rng(3)
+    u0 = 0.5 * g.standard_normal((5, n[2], n[1], n[0]))
+    k = oracle.delays(20, 6 * 12, 3, 2, 0, 6)
+    for stale in (False, True):
+        assert np.array_equal(
+            oracle.run3d(u0, n, p, 3, 0.05, 0.005, k, 20, alpha=(0.02, 0.11), stale=stale),
+            twin.run3d(u0, n, p, 3, 0.05, 0.005, k, 20, alpha=(0.02, 0.11), stale=stale))
+
+
+def test_scalar_convergence_uniform_velocity():
+    """Scalars advected by a uniform velocity U (an exact steady velocity) and
+    diffused with two different alpha: second order in dx for synchronous and
+    AT halos, first order for stale halos (Figure 2's pattern)."""
+    U, alpha, T, L = (0.3, -0.2, 0.5), (0.1, 0.04), 0.5, 2
+    rates = {}
+    for mode in ("sync", "at", "stale"):
+        errs = []
+        for n in (16, 32):
+            dx = 2 * np.pi / n
+            dt = 0.1 * dx * dx / max(alpha)
+            nst = int(round(T / dt))
+            vel = np.stack([np.full((n, n, n), c) for c in U])
+            ex = [ScalarUniform3D(a, U) for a in alpha]
+            u0 = np.concatenate([vel] + [e.phi(n, 0.0)[None] for e in ex], axis=0)
+            k = (np.zeros((nst, 48), np.int8) if mode == "sync"
+                 else oracle.delays(nst, 48, L, 2, 0, 3))
+            uT = oracle.run3d(u0, (n, n, n), (2, 2, 2), L, 0.07, dt, k, nst, alpha=alpha,
+                              stale=(mode == "stale"))
+            assert np.array_equal(uT[:3], vel)
+            errs.append([float(np.sqrt(np.mean((uT[3 + j] - ex[j].phi(n, nst * dt)) ** 2)))
+                         for j in range(2)])
+        rates[mode] = [math.log2(errs[0][j] / errs[1][j]) for j in range(2)]
+    for j in range(2):
+        assert abs(rates["sync"][j] - 2.0) < 0.15, rates
+        assert abs(rates["at"][j] - 2.0) < 0.15, rates
+        assert rates["stale"][j] < 1.5, rates
 
 
 # --------------------------------------------------------------------------
