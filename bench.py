@@ -211,7 +211,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--only", choices=["main", "all"], default="all")
-    ap.add_argument("--legs", default="plain,contracted,batched,adjoint,3d",
+    ap.add_argument("--legs", default="plain,contracted,batched,adjoint,3d,scalars",
                     help="comma-separated sub-measurements run with --only all")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fuse", type=int, default=None,
@@ -428,12 +428,15 @@ def bench_adjoint(args, torch, at, I):
             "n": N, "nsteps": nst, "ckpt_every": C}
 
 
-def bench_3d(args, torch, at, I):
-    """3D vector Burgers, 512^3 x 3 components, 8^3 blocks of 64^3, order 2,
-    L = 3, 200 steps."""
-    wl = I.wl_solenoidal_3d()
+def _bench_3d_run(args, torch, at, wl, alpha, tag):
+    """Autotuned kernel variant, then whole runs of wl.nsteps steps timed from a
+    restored snapshot; algorithmic bytes per point-update: NC = 3 + scalars
+    components in and out (16 NC B) plus the ring (publish 6 faces of NC
+    components; read levels n-k and n-k-1 of the faces with k > 0, a fraction
+    L/(L+1) of them under uniform delays)."""
+    nc = 3 + len(alpha)
     st = at.Stepper(dim=3, n=wl.n, p=wl.p, order=2, L=wl.L, nu=wl.nu, dt=wl.dt,
-                    nsteps_max=wl.nsteps, seed=wl.seed, dist=wl.dist)
+                    nsteps_max=wl.nsteps, seed=wl.seed, dist=wl.dist, alpha=alpha)
     u0 = torch.from_numpy(wl.u0).cuda()
     var = st.autotune(u0, 6)
     snap = st.snapshot(u0)
@@ -450,24 +453,36 @@ def bench_3d(args, torch, at, I):
         tm.stop()
     sec = tm.total_ms() * 1e-3 / reps
     npt = wl.npoints
-    # per point-update: 3 components in and out (48 B); ring: publish 6 faces,
-    # read m = 2 levels of the faces with k > 0 (L/(L+1) of them); delays
     bx = wl.n[0] // wl.p[0]
     face_frac = 6.0 / bx
-    ring_b = face_frac * 24 * (1 + 2 * wl.L / (wl.L + 1.0))
-    bpu = 48.0 + ring_b
+    ring_b = face_frac * 8.0 * nc * (1 + 2 * wl.L / (wl.L + 1.0))
+    bpu = 16.0 * nc + ring_b
     gbps = npt * wl.nsteps * bpu / sec / 1e9
-    eprint("[3d] variant %d" % var)
-    eprint("[3d] %s: %.2f ms/run, %.3g point-updates/s, %.0f GB/s (%.1f B/update)" %
-           (wl.name, sec * 1e3, npt * wl.nsteps / sec, gbps, bpu))
-    return {"value": npt * wl.nsteps / sec, "unit": "point-updates/s (3 components)",
+    eprint("[%s] variant %d" % (tag, var))
+    eprint("[%s] %s: %.2f ms/run, %.3g point-updates/s, %.0f GB/s (%.1f B/update)" %
+           (tag, wl.name, sec * 1e3, npt * wl.nsteps / sec, gbps, bpu))
+    return {"value": npt * wl.nsteps / sec, "unit": "point-updates/s (%d components)" % nc,
             "ms_per_run": round(sec * 1e3, 3), "hbm_gbps": round(gbps, 1),
             "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4), "bytes_per_update": round(bpu, 2),
             "workload": wl.name, "kernel_us_per_step": round(sec * 1e6 / wl.nsteps, 2),
             "kernel_variant": var}
 
 
-EXTRA = [("batched", bench_batched), ("adjoint", bench_adjoint), ("3d", bench_3d)]
+def bench_3d(args, torch, at, I):
+    """3D vector Burgers, 512^3 x 3 components, 8^3 blocks of 64^3, order 2,
+    L = 3, 200 steps."""
+    return _bench_3d_run(args, torch, at, I.wl_solenoidal_3d(), (), "3d")
+
+
+def bench_scalars(args, torch, at, I):
+    """3D vector Burgers with two passive scalars (Schmidt numbers 1 and 2),
+    512^3 x 5 components, 8^3 blocks of 64^3, order 2, L = 3, 200 steps."""
+    wl = I.wl_scalars_3d()
+    return _bench_3d_run(args, torch, at, wl, wl.extra["alpha"], "scalars")
+
+
+EXTRA = [("batched", bench_batched), ("adjoint", bench_adjoint), ("3d", bench_3d),
+         ("scalars", bench_scalars)]
 
 if __name__ == "__main__":
     main()

@@ -20,7 +20,10 @@
  *     coefficients to another article).
  *   * Central differences, forward Euler (section 3.2), for
  *     u_t + u u_x = nu u_xx (1D) and u_i,t + u_j d_j u_i = nu d_j d_j u_i (3D
- *     vector, section 3.1, Eq. (4)), periodic domain of side `length`.
+ *     vector, section 3.1, Eq. (4)), periodic domain of side `length`; in 3D
+ *     optionally with passive scalars phi_s,t + u_j d_j phi_s =
+ *     alpha_s d_j d_j phi_s (the second line of Eq. (4)), each advected by
+ *     the velocity and carried through the same AT halos.
  *   * The neighbour edges of past levels live in a circular buffer ("ring")
  *     of R levels, the analogue of the paper's circular receive buffers of
  *     T entries (section 5.2, Algorithm 2, Table 1).
@@ -28,8 +31,9 @@
  * Conventions for every call:
  *   * All field pointers (u, scratch, lambda, gradients, targets, outputs of
  *     reductions) are DEVICE pointers to contiguous binary64 arrays owned by
- *     the caller.  1D fields are double[n0].  3D fields are double[3][nz][ny][nx]
- *     (component-major, x fastest).
+ *     the caller.  1D fields are double[n0].  3D fields are
+ *     double[3 + nscalars][nz][ny][nx] (component-major, x fastest:
+ *     u_x, u_y, u_z, then the scalars).
  *   * The caller also owns the workspace (device memory of at least
  *     at_workspace_bytes() bytes, 256-byte aligned).  The library never
  *     allocates or frees device memory.  The opaque handles (at_ctx,
@@ -51,7 +55,8 @@
 extern "C" {
 #endif
 
-#define AT_ABI_VERSION 2
+#define AT_ABI_VERSION 3
+#define AT_MAX_SCALARS 4      /* passive scalars a 3D context may carry         */
 
 typedef enum {
     AT_OK = 0,
@@ -71,7 +76,7 @@ typedef enum {
 
 typedef struct at_config {
     int32_t abi_version;      /* must equal AT_ABI_VERSION                        */
-    int32_t dim;              /* 1 (scalar) or 3 (vector, 3 components)           */
+    int32_t dim;              /* 1 (scalar) or 3 (vector, 3 components + scalars) */
     int64_t n[3];             /* points per axis x, y, z (1D: n[1] = n[2] = 1)    */
     int32_t p[3];             /* tiles per axis (1D: p[1] = p[2] = 1)             */
     int32_t order;            /* 2 or 4 (3D: 2); halo width h = order / 2,
@@ -105,6 +110,10 @@ typedef struct at_config {
                                  dt*nu*c2 folded, u' = u + A2*T2 - (a*A1)*T1 --
                                  fewer instructions, same binary64 precision,
                                  results differ in the last bits */
+    int32_t nscalars;         /* 3D: passive scalars 0..AT_MAX_SCALARS (1D: 0)    */
+    int32_t reserved1;        /* must be 0                                        */
+    double alpha[AT_MAX_SCALARS]; /* diffusivity of each scalar, finite, >= 0;
+                                 entries past nscalars are ignored               */
     void *stream;             /* hipStream_t for all work of this context         */
     void *workspace;          /* device memory owned by the caller                */
     uint64_t workspace_bytes;

@@ -18,7 +18,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libat.so")
 
-AT_ABI_VERSION = 2
+AT_ABI_VERSION = 3
+AT_MAX_SCALARS = 4
 AT_OK, AT_ERR_ARG, AT_ERR_SHAPE, AT_ERR_DELAY, AT_ERR_HIP, AT_ERR_NOMEM, AT_ERR_STATE = \
     0, -1, -2, -3, -4, -5, -6
 DELAY_GENERATE, DELAY_HOST = 0, 1
@@ -56,6 +57,9 @@ class Config(ctypes.Structure):
         ("ckpt_every", ctypes.c_int32),
         ("fuse_steps", ctypes.c_int32),
         ("arith", ctypes.c_int32),
+        ("nscalars", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
+        ("alpha", ctypes.c_double * AT_MAX_SCALARS),
         ("stream", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_uint64),
@@ -145,7 +149,8 @@ def levels_for_order(order: int) -> int:
 def make_config(*, dim=1, n, p, order=2, L=0, nu, dt, nsteps_max, length=2 * math.pi,
                 halo_mode=0, adv_mode=0, adv_speed=0.0, delays=None, seed=0,
                 dist=DIST_UNIFORM, record=False, ckpt_every=0, fuse_steps=1,
-                stream=None, arith=0) -> Config:
+                stream=None, arith=0, alpha=()) -> Config:
+    """alpha: diffusivities of the passive scalars (3D only), one per scalar."""
     c = Config()
     c.abi_version = AT_ABI_VERSION
     c.dim = dim
@@ -166,6 +171,13 @@ def make_config(*, dim=1, n, p, order=2, L=0, nu, dt, nsteps_max, length=2 * mat
     c.ckpt_every = int(ckpt_every)
     c.fuse_steps = int(fuse_steps)
     c.arith = int(arith)
+    al = [float(a) for a in alpha]
+    if len(al) > AT_MAX_SCALARS:
+        raise ValueError("at most %d passive scalars" % AT_MAX_SCALARS)
+    c.nscalars = len(al)
+    c.reserved1 = 0
+    for j in range(AT_MAX_SCALARS):
+        c.alpha[j] = al[j] if j < len(al) else 0.0
     c.stream = stream
     c.workspace = None
     c.workspace_bytes = 0
@@ -189,25 +201,28 @@ def _alloc_workspace(nbytes: int, device) -> torch.Tensor:
 class Stepper:
     """One AT Burgers problem (1D scalar or 3D vector) on one device.
 
-    Fields are torch float64 CUDA tensors: 1D shape (n,), 3D shape (3, nz, ny, nx).
+    Fields are torch float64 CUDA tensors: 1D shape (n,), 3D shape
+    (3 + len(alpha), nz, ny, nx): the velocity, then the passive scalars with
+    diffusivities ``alpha``.
     ``delays`` (int8 array [nsteps_max][F]) selects host mode; otherwise the
     library generates them from ``seed`` and ``dist``."""
 
     def __init__(self, *, dim=1, n, p, order=2, L=0, nu, dt, nsteps_max,
                  length=2 * math.pi, halo_mode=0, adv_mode=0, adv_speed=0.0, delays=None,
                  seed=0, dist=DIST_UNIFORM, record=False, ckpt_every=0, fuse_steps=1,
-                 device="cuda", arith=0):
+                 device="cuda", arith=0, alpha=()):
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
         self.cfg = make_config(dim=dim, n=n, p=p, order=order, L=L, nu=nu, dt=dt,
                                nsteps_max=nsteps_max, length=length, halo_mode=halo_mode,
                                adv_mode=adv_mode, adv_speed=adv_speed, delays=delays,
                                seed=seed, dist=dist, record=record, ckpt_every=ckpt_every,
-                               fuse_steps=fuse_steps, arith=arith,
+                               fuse_steps=fuse_steps, arith=arith, alpha=alpha,
                                stream=ctypes.c_void_p(self.stream.cuda_stream))
         self.dim = dim
         self.shape = (int(self.cfg.n[0]),) if dim == 1 else \
-            (3, int(self.cfg.n[2]), int(self.cfg.n[1]), int(self.cfg.n[0]))
+            (3 + int(self.cfg.nscalars), int(self.cfg.n[2]), int(self.cfg.n[1]),
+             int(self.cfg.n[0]))
         self.numel = int(np.prod(self.shape))
         self.nfaces = (2 if dim == 1 else 6) * int(np.prod([self.cfg.p[a] for a in range(3)]))
         self._ctx = ctypes.c_void_p(None)

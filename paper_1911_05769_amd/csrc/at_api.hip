@@ -115,6 +115,13 @@ at_status derive(const at_config *c, Derived &d)
         return fail(AT_ERR_ARG, "fuse_steps must be in 0..%d", kMaxFuse);
     if (c->arith != 0 && c->arith != 1) return fail(AT_ERR_ARG, "arith must be 0 or 1");
     if (c->arith == 1 && c->dim != 1) return fail(AT_ERR_ARG, "arith 1 is 1D only");
+    if (c->reserved1 != 0) return fail(AT_ERR_ARG, "reserved1 must be 0");
+    if (c->nscalars < 0 || c->nscalars > AT_MAX_SCALARS)
+        return fail(AT_ERR_ARG, "nscalars must be in 0..%d", AT_MAX_SCALARS);
+    if (c->nscalars > 0 && c->dim != 3) return fail(AT_ERR_ARG, "passive scalars are 3D only");
+    for (int s = 0; s < c->nscalars; ++s)
+        if (!(c->alpha[s] >= 0.0) || !isfinite(c->alpha[s]))
+            return fail(AT_ERR_ARG, "alpha[%d] must be finite and >= 0", s);
     if (c->record) {
         if (c->dim != 1) return fail(AT_ERR_ARG, "record mode (adjoint) is 1D only");
         if (c->ckpt_every < 1) return fail(AT_ERR_ARG, "record mode needs ckpt_every >= 1");
@@ -343,8 +350,11 @@ at_status launch_any(at_ctx *c, const double *uin, double *uout, int64_t n0, int
     return at3_launch(c, uin, uout, n0, s, publish);
 }
 
-// doubles in one field: N (1D) or 3N (3D, three components)
-int64_t field_doubles(const at_ctx *c) { return (c->d.dim == 1 ? 1 : 3) * c->d.N; }
+// doubles in one field: N (1D) or (3 + nscalars) N (3D: velocity, then scalars)
+int64_t field_doubles(const at_ctx *c)
+{
+    return (c->d.dim == 1 ? 1 : 3 + c->cfg.nscalars) * c->d.N;
+}
 
 int max_fuse(const at_ctx *c)
 {
@@ -461,6 +471,8 @@ at_status at_init(const at_config *cfg, at_ctx **out)
     c->gnu = cfg->record ? (double *)(base + L.gnu) : nullptr;
     c->n = 0;
     c->variant = 0;
+    if (d.dim == 3)   // the first variant with a build for this component count
+        while (!at3_variant_ok(&c->cfg, c->variant)) ++c->variant;
     c->fuse = cfg->fuse_steps > 0 ? std::min(cfg->fuse_steps, max_fuse(c)) : 1;
     hipError_t e = hipSuccess;
     if (cfg->delay_mode == AT_DELAY_GENERATE)

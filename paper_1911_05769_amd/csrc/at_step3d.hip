@@ -1,7 +1,11 @@
 // 3D vector stepper of libat.so for gfx950.
 //
 // Method: u_i,t + u_j d_j u_i = nu d_j d_j u_i (paper section 3.1, Eq. (4)),
-// i, j over x, y, z, on a periodic grid split into Px x Py x Pz blocks,
+// i, j over x, y, z, plus passive scalars phi_s,t + u_j d_j phi_s =
+// alpha_s d_j d_j phi_s (the second line of Eq. (4)): NC = 3 + nscalars
+// components, component c diffused with kappa_c (nu for the velocity, alpha_s
+// for the scalars) and advected by the velocity, on a periodic grid split
+// into Px x Py x Pz blocks,
 // second-order central differences and forward Euler (section 3.2).  A point
 // on a block face reads its neighbour across the face through an AT halo:
 // the neighbour block's face value extrapolated in time from levels n-k and
@@ -10,15 +14,15 @@
 // neighbour's current value.  Fixed evaluation order (contraction off):
 //   D1_a = (r - l)*c1_a,  D2_a = ((r - 2u) + l)*c2_a       for a = x, y, z
 //   lap = (D2_x + D2_y) + D2_z,  adv = (u_x*D1_x + u_y*D1_y) + u_z*D1_z
-//   u' = u + dt*(nu*lap - adv)
+//   u' = u + dt*(kappa_c*lap - adv)
 //
-// Layout: fields double[3][nz][ny][nx] (x fastest).  Ring level: per block,
-// faces x-low, x-high, y-low, y-high, z-low, z-high, each [3][plane] with the
+// Layout: fields double[NC][nz][ny][nx] (x fastest).  Ring level: per block,
+// faces x-low, x-high, y-low, y-high, z-low, z-high, each [NC][plane] with the
 // plane indexed (z, y) for x-faces, (z, x) for y-faces, (y, x) for z-faces.
 //
 // Work decomposition (2.5D): a workgroup of 64 x 8 threads owns a 64 x 8 x-y
 // tile (one point per thread) and marches through ZC planes in z.  Each
-// thread keeps the z-1, z, z+1 values (3 components) in registers and has
+// thread keeps the z-1, z, z+1 values (NC components) in registers and has
 // planes z+2 and z+3 in flight; the current plane with one-point rims sits in a
 // double-buffered LDS tile for the x and y neighbours (one barrier per
 // plane).  Block faces inside the tile are handled per point (any block
@@ -53,8 +57,9 @@ struct Step3D {
     int64_t n;
     int32_t R, stale, publish, ZC;
     int32_t slot0;            // n mod R
-    int32_t pad0;
-    double nu, dt, c1[3], c2[3];
+    int32_t nc;               // components: 3 + passive scalars
+    double dt, c1[3], c2[3];
+    double kappa[3 + AT_MAX_SCALARS];   // diffusivity per component
 };
 
 namespace {
@@ -62,14 +67,19 @@ namespace {
 constexpr int TX = 64;        // tile width in x (one wave64 per row)
 constexpr int kZB = 64;       // z-blocks one chunk of the aligned kernel may span
 
+// waves per SIMD a variant asks for; from 6 components on scaled down for
+// the larger register footprint (measured at 512^3: the unscaled bound is
+// faster up to 5 components, the scaled one above)
+constexpr int waves_for(int minw, int nc) { return nc <= 5 ? minw : (minw * 3 / nc > 0 ? minw * 3 / nc : 1); }
+
 __device__ __forceinline__ int wrap32(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 // TY rows per tile (= waves per workgroup, one row per thread); PF planes
 // prefetched ahead (1 or 2); MINW waves per SIMD the register budget allows.
-template <int TY, int PF, int MINW>
-__global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
+template <int TY, int PF, int MINW, int NC>
+__global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d(Step3D A)
 {
-    __shared__ double pl[2][3][TY + 2][TX + 2];
+    __shared__ double pl[2][NC][TY + 2][TX + 2];
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int nx = (int)A.nx, ny = (int)A.ny, nz = (int)A.nz;
     const int X0 = blockIdx.x * TX, Y0 = blockIdx.y * TY;
@@ -82,7 +92,8 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
     const int plane = nx * ny;
     const int bx = x / A.Wx, lx = x - bx * A.Wx;
     const int by = y / A.Wy, ly = y - by * A.Wy;
-    const double *U0 = A.uin, *U1 = A.uin + A.npt, *U2 = A.uin + 2 * A.npt;
+    const double *U0 = A.uin;
+    const int64_t npt = A.npt;
     // rim loads of this thread (lanes 0/1: x rims of its row; waves 0/1: y rims)
     const bool xrim = tx < 2 && ty < hy;
     const int xs = tx == 0 ? wrap32(X0 - 1, nx) : wrap32(X0 + wx, nx);
@@ -93,13 +104,12 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
     const int col = y * nx + x;
 
     auto ld3 = [&](int off, double *v, bool on) {
-        v[0] = on ? U0[off] : 0.0;
-        v[1] = on ? U1[off] : 0.0;
-        v[2] = on ? U2[off] : 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = on ? U0[c * npt + off] : 0.0;
     };
     // register pipeline: planes z-1, z, z+1 in use, z+2 (and z+3 when PF = 2)
     // in flight; rims of plane z+1 (and z+2) in flight
-    double zm[3], zc[3], zp[3], zq[3], zr[3], rx[3], ry[3], rx2[3], ry2[3];
+    double zm[NC], zc[NC], zp[NC], zq[NC], zr[NC], rx[NC], ry[NC], rx2[NC], ry2[NC];
     ld3(wrap32(Z0 - 1, nz) * plane + col, zm, act);
     ld3(Z0 * plane + col, zc, act);
     ld3(wrap32(Z0 + 1, nz) * plane + col, zp, act);
@@ -108,7 +118,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
     ld3(Z0 * plane + ys * nx + x, ry, yrim);
     // plane Z0 into buffer 0
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < NC; ++c) {
         if (act) pl[0][c][ty + 1][tx + 1] = zc[c];
         if (xrim) pl[0][c][ty + 1][xcol] = rx[c];
         if (yrim) pl[0][c][yrow][tx + 1] = ry[c];
@@ -151,9 +161,9 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
             const int kzh = lz == A.Wz - 1 ? kc[5] : 0;
             const int px = lz * A.Wy + ly, py = lz * A.Wx + lx, pz = ly * A.Wx + lx;
             // neighbours: x/y from the LDS tile, z from registers
-            double nb[6][3];
+            double nb[6][NC];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < NC; ++c) {
                 nb[0][c] = pl[buf][c][ty + 1][tx];
                 nb[1][c] = pl[buf][c][ty + 1][tx + 2];
                 nb[2][c] = pl[buf][c][ty][tx + 1];
@@ -182,7 +192,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
                     const double *r1 = A.ring + s1 * A.level + off;
                     const double dk = (double)kk;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) {
+                    for (int c = 0; c < NC; ++c) {
                         const double v0 = r0[c * A.psz[a]];
                         nb[f][c] = A.stale ? v0 : v0 + dk * (v0 - r1[c * A.psz[a]]);
                     }
@@ -190,9 +200,9 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
             }
             const double ux = zc[0], uy = zc[1], uz = zc[2];
             double *out = A.uout + (int64_t)z * plane + col;
-            double ov[3];
+            double ov[NC];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < NC; ++c) {
                 const double u = zc[c];
                 const double xl = nb[0][c], xr = nb[1][c], yl = nb[2][c], yh = nb[3][c];
                 const double zl = nb[4][c], zh = nb[5][c];
@@ -201,7 +211,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
                 const double D1z = (zh - zl) * A.c1[2], D2z = ((zh - 2.0 * u) + zl) * A.c2[2];
                 const double lap = (D2x + D2y) + D2z;
                 const double adv = (ux * D1x + uy * D1y) + uz * D1z;
-                ov[c] = u + A.dt * (A.nu * lap - adv);
+                ov[c] = u + A.dt * (A.kappa[c] * lap - adv);
                 out[c * A.npt] = ov[c];
             }
             // publish the level-(n+1) values of points on block faces
@@ -210,7 +220,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
             if (A.publish && onface) {
                 double *base = A.ring + slot * A.level + b * A.bstride;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
+                for (int c = 0; c < NC; ++c) {
                     const double u = ov[c];
                     if (lx == 0) base[A.foff[0] + c * A.psz[0] + px] = u;
                     if (lx == A.Wx - 1) base[A.foff[1] + c * A.psz[0] + px] = u;
@@ -224,7 +234,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
         if (more) {
             // plane z+1 into the other buffer (its readers finished before the barrier)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < NC; ++c) {
                 if (act) pl[buf ^ 1][c][ty + 1][tx + 1] = zp[c];
                 if (xrim) pl[buf ^ 1][c][ty + 1][xcol] = rx[c];
                 if (yrim) pl[buf ^ 1][c][yrow][tx + 1] = ry[c];
@@ -232,7 +242,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
             if (PF == 2) {                                            // rims of plane z+3
                 const int zo = wrap32(z + 3, nz) * plane;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) { rx[c] = rx2[c]; ry[c] = ry2[c]; }
+                for (int c = 0; c < NC; ++c) { rx[c] = rx2[c]; ry[c] = ry2[c]; }
                 ld3(zo + y * nx + xs, rx2, xrim && z + 3 < Z1);
                 ld3(zo + ys * nx + x, ry2, yrim && z + 3 < Z1);
             } else {                                                  // rims of plane z+2
@@ -242,7 +252,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
             }
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < NC; ++c) {
             zm[c] = zc[c]; zc[c] = zp[c]; zp[c] = zq[c];
             if (PF == 2) zq[c] = zr[c];
         }
@@ -250,34 +260,34 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d(Step3D A)
 }
 
 
-// One neighbour value triple (3 components) for a tile rim or a z face.
+// One neighbour value of all NC components for a tile rim or a z face.
 // Across a block face it comes from the ring: levels n-k and n-k-1 of the
 // neighbour block's face (k = 0: level n, which the previous step published
 // there, contiguous along the face); inside a block, from the field (loaded
-// twice from the same address).  Every lane of a role issues the same six
+// twice from the same address).  Every lane of a role issues the same 2 NC
 // loads whatever k is, so the wait counts stay static and no later wait
 // drains the planes in flight.
-struct Nb3 {
-    double a0, a1, a2;        // level n-k (or the field)
-    double b0, b1, b2;        // level n-k-1 (or a repeat of a)
+template <int NC>
+struct NbC {
+    double a[NC];             // level n-k (or the field)
+    double b[NC];             // level n-k-1 (or a repeat of a)
     int k;
 };
 
-__device__ __forceinline__ Nb3 load_nb3(const double *ring, const double *field, bool face, int k,
-                                        bool stale, int64_t oring0, int64_t oring1, int64_t cring,
-                                        int64_t ofield, int64_t cfield)
+template <int NC>
+__device__ __forceinline__ NbC<NC> load_nbc(const double *ring, const double *field, bool face,
+                                            int k, bool stale, int64_t oring0, int64_t oring1,
+                                            int64_t cring, int64_t ofield, int64_t cfield)
 {
     const double *p0 = face ? ring + oring0 : field + ofield;
     const double *p1 = (k > 0 && !stale) ? ring + oring1 : p0;
     const int64_t cs = face ? cring : cfield;
-    Nb3 r;
+    NbC<NC> r;
     r.k = k;
-    r.a0 = p0[0];
-    r.a1 = p0[cs];
-    r.a2 = p0[2 * cs];
-    r.b0 = p1[0];
-    r.b1 = p1[cs];
-    r.b2 = p1[2 * cs];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r.a[c] = p0[c * cs];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r.b[c] = p1[c * cs];
     return r;
 }
 
@@ -297,11 +307,11 @@ __device__ __forceinline__ double at_h(int k, bool stale, double v0, double v1)
 // the same branch-free stencil (the split of section 5.2).  The face delays
 // of the chunk are copied to LDS first, and every load inside the march is
 // consumed one plane after it is issued.
-template <int TY, int MINW, int PF>
-__global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
+template <int TY, int MINW, int PF, int NC>
+__global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d_aligned(Step3D A)
 {
     static_assert(PF == 1 || PF == 2, "plane queue of 2 or 3 slots");
-    __shared__ double pl[2][3][TY + 2][TX + 2];
+    __shared__ double pl[2][NC][TY + 2][TX + 2];
     __shared__ int8_t kdl[6 * kZB];
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int nx = (int)A.nx, ny = (int)A.ny, nz = (int)A.nz;
@@ -380,49 +390,47 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
     // planes z-1 and z in registers; planes z+1 .. z+PF in a queue of PF+1
     // register slots that rotates by renaming (the loop is unrolled PF+1
     // times): a slot whose load is still in flight is never copied
-    double zm0, zm1, zm2, zc0, zc1, zc2;
-    double qa[3], qb[3], qc[3];
-    zm0 = U0[wrap32(Z0 - 1, nz) * plane + col];
-    zm1 = U0[npt + wrap32(Z0 - 1, nz) * plane + col];
-    zm2 = U0[2 * npt + wrap32(Z0 - 1, nz) * plane + col];
-    zc0 = U0[Z0 * plane + col];
-    zc1 = U0[npt + Z0 * plane + col];
-    zc2 = U0[2 * npt + Z0 * plane + col];
+    double zm[NC], zc[NC];
+    double qa[NC], qb[NC], qc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) zm[c] = U0[c * npt + wrap32(Z0 - 1, nz) * plane + col];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) zc[c] = U0[c * npt + Z0 * plane + col];
     {
         const int o = wrap32(Z0 + 1, nz) * plane + col;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) qa[c] = U0[c * npt + o];
+        for (int c = 0; c < NC; ++c) qa[c] = U0[c * npt + o];
     }
     if (PF == 2) {
         const int o = wrap32(Z0 + 2, nz) * plane + col;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) qb[c] = U0[c * npt + o];
+        for (int c = 0; c < NC; ++c) qb[c] = U0[c * npt + o];
     }
     __syncthreads();                                      // kdl ready
 
     // loads of plane p's rim values, consumed one plane later
-    Nb3 rr{};
+    NbC<NC> rr{};
     auto issue = [&](int p) {
         const int bz = p / Wz, lz = p - bz * Wz;
         if (rim_role) {
             const int k = r_face ? kdl[6 * (bz - bz0) + r_fidx] : 0;
             const int64_t off = (r_blk + (int64_t)bz * PyPx) * bstride + r_foff +
                                 (int64_t)lz * r_lzmul + r_pos;
-            rr = load_nb3(A.ring, U0, r_face, k, stale, lvl(k) + off, lvl(k + 1) + off, r_cring,
-                          (int64_t)p * plane + r_field, npt);
+            rr = load_nbc<NC>(A.ring, U0, r_face, k, stale, lvl(k) + off, lvl(k + 1) + off,
+                              r_cring, (int64_t)p * plane + r_field, npt);
         }
     };
     // plane p's rim values into LDS buffer bf
     auto finish_rims = [&](int bf) {
         if (rim_role) {
-            (&pl[bf][0][0][0])[r_lds] = at_h(rr.k, stale, rr.a0, rr.b0);
-            (&pl[bf][1][0][0])[r_lds] = at_h(rr.k, stale, rr.a1, rr.b1);
-            (&pl[bf][2][0][0])[r_lds] = at_h(rr.k, stale, rr.a2, rr.b2);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                (&pl[bf][c][0][0])[r_lds] = at_h(rr.k, stale, rr.a[c], rr.b[c]);
         }
     };
     // z neighbour of plane p across a block face (uniform over the tile):
     // loads issued at the start of the step before, consumed at its end
-    Nb3 zr{};
+    NbC<NC> zr{};
     int zside = 0;
     auto issue_z = [&](int p) {
         const int bz = p / Wz, lz = p - bz * Wz;
@@ -433,56 +441,57 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
             const int nbz = wrap32(bz + (zside ? 1 : -1), A.Pz);
             const int64_t off = (z_blk + (int64_t)nbz * PyPx) * bstride +
                                 (zside ? zhi_foff : zlo_foff) + ly * Wx + lx;
-            zr = load_nb3(A.ring, U0, true, k, stale, lvl(k) + off, lvl(k + 1) + off, psz2, 0, npt);
+            zr = load_nbc<NC>(A.ring, U0, true, k, stale, lvl(k) + off, lvl(k + 1) + off, psz2, 0,
+                              npt);
         }
     };
 
-    double hz0 = 0.0, hz1 = 0.0, hz2 = 0.0;
+    double hz[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) hz[c] = 0.0;
     bool hz_lo = false, hz_hi = false;      // plane's z neighbour replaced by hz (low / high)
     auto take_z = [&]() {
         hz_lo = hz_hi = false;
         if (zr.k > 0) {
-            hz0 = at_h(zr.k, stale, zr.a0, zr.b0);
-            hz1 = at_h(zr.k, stale, zr.a1, zr.b1);
-            hz2 = at_h(zr.k, stale, zr.a2, zr.b2);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) hz[c] = at_h(zr.k, stale, zr.a[c], zr.b[c]);
             hz_lo = zside == 0;
             hz_hi = zside == 1;
         }
     };
     issue_z(Z0);
     issue(Z0);
-    pl[0][0][ty + 1][tx + 1] = zc0;
-    pl[0][1][ty + 1][tx + 1] = zc1;
-    pl[0][2][ty + 1][tx + 1] = zc2;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) pl[0][c][ty + 1][tx + 1] = zc[c];
     finish_rims(0);
     take_z();
     if (Z0 + 1 < Z1) issue(Z0 + 1);
     const int64_t slot = A.slot0 + 1 == A.R ? 0 : A.slot0 + 1;   // level n+1 is published
     const double c10 = A.c1[0], c11 = A.c1[1], c12 = A.c1[2];
     const double c20 = A.c2[0], c21 = A.c2[1], c22 = A.c2[2];
-    const double nu = A.nu, dt = A.dt;
+    const double dt = A.dt;
 
     int bz = Z0 / Wz, lz = Z0 - bz * Wz;
     // one plane: znx holds plane z+1 (complete), zld receives plane z+1+PF
-    auto body = [&](int z, double (&znx)[3], double (&zld)[3]) {
+    auto body = [&](int z, double (&znx)[NC], double (&zld)[NC]) {
         if (lz == Wz) { lz = 0; ++bz; }
         const int buf = (z - Z0) & 1;
         const bool more = z + 1 < Z1;
         {
             const int o = wrap32(z + 1 + PF, nz) * plane + col;   // past Z1: unused, in bounds
 #pragma unroll
-            for (int c = 0; c < 3; ++c) zld[c] = U0[c * npt + o];
+            for (int c = 0; c < NC; ++c) zld[c] = U0[c * npt + o];
         }
         if (more) issue_z(z + 1);
         __syncthreads();
-        const double ux = zc0, uy = zc1, uz = zc2;
+        const double ux = zc[0], uy = zc[1], uz = zc[2];
         double *out = A.uout + (int64_t)z * plane + col;
-        double ov[3];
+        double ov[NC];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double u = c == 0 ? zc0 : (c == 1 ? zc1 : zc2);
-            const double zmc = c == 0 ? zm0 : (c == 1 ? zm1 : zm2);
-            const double hzc = c == 0 ? hz0 : (c == 1 ? hz1 : hz2);
+        for (int c = 0; c < NC; ++c) {
+            const double u = zc[c];
+            const double zmc = zm[c];
+            const double hzc = hz[c];
             const double xl = pl[buf][c][ty + 1][tx], xh = pl[buf][c][ty + 1][tx + 2];
             const double yl = pl[buf][c][ty][tx + 1], yh = pl[buf][c][ty + 2][tx + 1];
             const double zl = hz_lo ? hzc : zmc;
@@ -492,7 +501,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
             const double D1z = (zh - zl) * c12, D2z = ((zh - 2.0 * u) + zl) * c22;
             const double lap = (D2x + D2y) + D2z;
             const double adv = (ux * D1x + uy * D1y) + uz * D1z;
-            ov[c] = u + dt * (nu * lap - adv);
+            ov[c] = u + dt * (A.kappa[c] * lap - adv);
             out[c * npt] = ov[c];
         }
         // publish the level-(n+1) values of points on block faces
@@ -501,7 +510,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
             double *base = A.ring + slot * level + (((int64_t)bz * Py + by) * Px + bx) * bstride;
             const int px = lz * Wy + ly, py = lz * Wx + lx, pz = ly * Wx + lx;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < NC; ++c) {
                 const double u = ov[c];
                 if (lx == 0) base[A.foff[0] + c * psz0 + px] = u;
                 if (lx == Wx - 1) base[A.foff[1] + c * psz0 + px] = u;
@@ -513,15 +522,14 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
         }
         if (more) {
             // plane z+1: interior, rims and z neighbour (loads issued one plane ago)
-            pl[buf ^ 1][0][ty + 1][tx + 1] = znx[0];
-            pl[buf ^ 1][1][ty + 1][tx + 1] = znx[1];
-            pl[buf ^ 1][2][ty + 1][tx + 1] = znx[2];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) pl[buf ^ 1][c][ty + 1][tx + 1] = znx[c];
             finish_rims(buf ^ 1);
             take_z();
             if (z + 2 < Z1) issue(z + 2);
         }
-        zm0 = zc0; zm1 = zc1; zm2 = zc2;
-        zc0 = znx[0]; zc1 = znx[1]; zc2 = znx[2];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) { zm[c] = zc[c]; zc[c] = znx[c]; }
         ++lz;
     };
     int z = Z0;
@@ -547,7 +555,7 @@ __global__ __launch_bounds__(TX * TY, MINW) void k_step3d_aligned(Step3D A)
 // reads its x and y neighbours straight from global memory (L1/L2 hits: the
 // same rows are the neighbouring threads' own loads).  No LDS, no barrier, so
 // each wave advances on its own and many loads are in flight per wave.
-template <int TY>
+template <int TY, int NC>
 __global__ __launch_bounds__(TX * TY) void k_step3d_direct(Step3D A)
 {
     const int tx = threadIdx.x, ty = threadIdx.y;
@@ -565,9 +573,9 @@ __global__ __launch_bounds__(TX * TY) void k_step3d_direct(Step3D A)
     const int by = y / A.Wy, ly = y - by * A.Wy;
     const double *U0 = A.uin;
     auto U = [&](int c, int off) -> double { return U0[(int64_t)c * A.npt + off]; };
-    double zm[3], zc[3], zp[3], zq[3];
+    double zm[NC], zc[NC], zp[NC], zq[NC];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < NC; ++c) {
         zm[c] = U(c, wrap32(Z0 - 1, nz) * plane + col);
         zc[c] = U(c, Z0 * plane + col);
         zp[c] = U(c, wrap32(Z0 + 1, nz) * plane + col);
@@ -580,9 +588,9 @@ __global__ __launch_bounds__(TX * TY) void k_step3d_direct(Step3D A)
         if (lz == A.Wz) { lz = 0; ++bz; }
         const bool more = z + 1 < Z1;
         const int po = z * plane;
-        double nb[6][3];
+        double nb[6][NC];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < NC; ++c) {
             zq[c] = more ? U(c, wrap32(z + 2, nz) * plane + col) : 0.0;
             nb[0][c] = U(c, po + y * nx + xm);
             nb[1][c] = U(c, po + y * nx + xp);
@@ -623,7 +631,7 @@ __global__ __launch_bounds__(TX * TY) void k_step3d_direct(Step3D A)
                 const double *r1 = A.ring + s1 * A.level + off;
                 const double dk = (double)kk;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
+                for (int c = 0; c < NC; ++c) {
                     const double v0 = r0[c * A.psz[a]];
                     nb[f][c] = A.stale ? v0 : v0 + dk * (v0 - r1[c * A.psz[a]]);
                 }
@@ -631,9 +639,9 @@ __global__ __launch_bounds__(TX * TY) void k_step3d_direct(Step3D A)
         }
         const double ux = zc[0], uy = zc[1], uz = zc[2];
         double *out = A.uout + (int64_t)po + col;
-        double ov[3];
+        double ov[NC];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
+        for (int c = 0; c < NC; ++c) {
             const double u = zc[c];
             const double xl = nb[0][c], xr = nb[1][c], yl = nb[2][c], yh = nb[3][c];
             const double zl = nb[4][c], zh = nb[5][c];
@@ -642,14 +650,14 @@ __global__ __launch_bounds__(TX * TY) void k_step3d_direct(Step3D A)
             const double D1z = (zh - zl) * A.c1[2], D2z = ((zh - 2.0 * u) + zl) * A.c2[2];
             const double lap = (D2x + D2y) + D2z;
             const double adv = (ux * D1x + uy * D1y) + uz * D1z;
-            ov[c] = u + A.dt * (A.nu * lap - adv);
+            ov[c] = u + A.dt * (A.kappa[c] * lap - adv);
             out[c * A.npt] = ov[c];
         }
         if (A.publish && (lx == 0 || lx == A.Wx - 1 || ly == 0 || ly == A.Wy - 1 || lz == 0 ||
                           lz == A.Wz - 1)) {
             double *base = A.ring + slot * A.level + b * A.bstride;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
+            for (int c = 0; c < NC; ++c) {
                 const double u = ov[c];
                 if (lx == 0) base[A.foff[0] + c * A.psz[0] + px] = u;
                 if (lx == A.Wx - 1) base[A.foff[1] + c * A.psz[0] + px] = u;
@@ -660,7 +668,7 @@ __global__ __launch_bounds__(TX * TY) void k_step3d_direct(Step3D A)
             }
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) { zm[c] = zc[c]; zc[c] = zp[c]; zp[c] = zq[c]; }
+        for (int c = 0; c < NC; ++c) { zm[c] = zc[c]; zc[c] = zp[c]; zp[c] = zq[c]; }
     }
 }
 
@@ -692,6 +700,12 @@ __global__ __launch_bounds__(256) void k3_publish(Step3D A)
     }
 }
 
+// LDS of the plane tiles of a TY-row variant carrying NC components; variants
+// above the 160 KiB a gfx950 workgroup may allocate are not instantiated
+constexpr size_t kMaxLds = 160 * 1024;
+constexpr size_t tile_lds(int TY, int NC) { return 2ull * NC * (TY + 2) * (TX + 2) * 8 + 6 * kZB; }
+constexpr bool lds_fits(int TY, int NC) { return tile_lds(TY, NC) <= kMaxLds; }
+
 int zchunk(int64_t nz, int64_t tiles_xy)
 {
     // enough workgroups to fill 256 CUs several times over, long z runs otherwise
@@ -709,6 +723,8 @@ using namespace atk;
 at_status at3_check(const at_config *c)
 {
     if (c->order != 2) return at_fail(AT_ERR_ARG, "3D stepper is order 2");
+    if (c->nscalars < 0 || c->nscalars > AT_MAX_SCALARS)
+        return at_fail(AT_ERR_ARG, "nscalars out of range");
     for (int a = 0; a < 3; ++a)
         if (c->n[a] / c->p[a] < 2) return at_fail(AT_ERR_SHAPE, "3D block narrower than 2");
     if (c->n[0] * c->n[1] * c->n[2] >= ((int64_t)1 << 31))
@@ -716,10 +732,13 @@ at_status at3_check(const at_config *c)
     return AT_OK;
 }
 
+static int ncomp(const at_config *c) { return 3 + c->nscalars; }
+
+// doubles of one block in a ring level: two faces per axis, NC components each
 static int64_t block_stride(const at_config *c)
 {
     const int64_t Wx = c->n[0] / c->p[0], Wy = c->n[1] / c->p[1], Wz = c->n[2] / c->p[2];
-    return 6 * (Wy * Wz + Wx * Wz + Wx * Wy);
+    return 2 * ncomp(c) * (Wy * Wz + Wx * Wz + Wx * Wy);
 }
 
 uint64_t at3_ring_level_doubles(const at_config *c)
@@ -737,11 +756,17 @@ static int k3_rows(int var)
     static const int r[15] = {8, 8, 4, 4, 16, 16, 8, 16, 4, 4, 8, 16, 8, 8, 16};
     return r[var < 0 || var > 14 ? 0 : var];
 }
-// variants 6..8 need block widths that are multiples of the tile
+static bool is_direct(int var) { return var >= 9 && var <= 11; }
+static bool is_aligned(int var) { return (var >= 6 && var <= 8) || var >= 12; }
+
+// aligned variants need block widths that are multiples of the tile; tiled
+// variants need their LDS planes for NC components within a workgroup's LDS
 bool at3_variant_ok(const at_config *c, int var)
 {
     if (var < 0 || var > 14) return false;
-    if (var < 6 || (var > 8 && var < 12)) return true;
+    const int nc = ncomp(c);
+    if (!is_direct(var) && tile_lds(k3_rows(var), nc) > kMaxLds) return false;
+    if (!is_aligned(var)) return true;
     const int64_t Wx = c->n[0] / c->p[0], Wy = c->n[1] / c->p[1];
     return Wx % TX == 0 && Wy % k3_rows(var) == 0;
 }
@@ -764,21 +789,23 @@ static void fill_step3d(at_ctx *ctx, const double *uin, double *uout, int64_t n0
     A.psz[0] = (int64_t)A.Wy * A.Wz;
     A.psz[1] = (int64_t)A.Wx * A.Wz;
     A.psz[2] = (int64_t)A.Wx * A.Wy;
+    const int64_t nc = ncomp(c);
+    A.nc = (int32_t)nc;
     A.foff[0] = 0;
-    A.foff[1] = 3 * A.psz[0];
-    A.foff[2] = 6 * A.psz[0];
-    A.foff[3] = 6 * A.psz[0] + 3 * A.psz[1];
-    A.foff[4] = 6 * A.psz[0] + 6 * A.psz[1];
-    A.foff[5] = 6 * A.psz[0] + 6 * A.psz[1] + 3 * A.psz[2];
+    A.foff[1] = nc * A.psz[0];
+    A.foff[2] = 2 * nc * A.psz[0];
+    A.foff[3] = 2 * nc * A.psz[0] + nc * A.psz[1];
+    A.foff[4] = 2 * nc * (A.psz[0] + A.psz[1]);
+    A.foff[5] = 2 * nc * (A.psz[0] + A.psz[1]) + nc * A.psz[2];
     A.n = n0;
     A.R = at_ctx_R(ctx);
     A.slot0 = (int32_t)(n0 % A.R);
     A.stale = c->halo_mode;
     A.publish = publish;
-    A.nu = c->nu;
+    for (int k = 0; k < 3 + AT_MAX_SCALARS; ++k)
+        A.kappa[k] = k < 3 ? c->nu : (k - 3 < c->nscalars ? c->alpha[k - 3] : 0.0);
     A.dt = c->dt;
     A.ZC = 0;
-    A.pad0 = 0;
     at_ctx_coefs(ctx, A.c1, A.c2);
 }
 
@@ -794,6 +821,40 @@ at_status at3_publish(at_ctx *ctx, const double *u, int64_t n)
     return AT_OK;
 }
 
+// The variant table: (tile rows, prefetch depth, waves per SIMD) per kernel
+// family; false when the variant has no build for NC components.
+template <int NC>
+static bool launch3(int var, dim3 grid, dim3 block, hipStream_t st, const Step3D &A)
+{
+#define K3_TILED(KERNEL, TY)                                                         \
+    do {                                                                             \
+        if constexpr (lds_fits(TY, NC)) {                                            \
+            hipLaunchKernelGGL(KERNEL, grid, block, 0, st, A);                      \
+            return true;                                                             \
+        }                                                                            \
+        return false;                                                                \
+    } while (0)
+    switch (var) {
+    case 0: K3_TILED((k_step3d<8, 1, 4, NC>), 8);
+    case 1: K3_TILED((k_step3d<8, 2, 4, NC>), 8);
+    case 2: K3_TILED((k_step3d<4, 2, 4, NC>), 4);
+    case 3: K3_TILED((k_step3d<4, 2, 3, NC>), 4);
+    case 4: K3_TILED((k_step3d<16, 1, 2, NC>), 16);
+    case 5: K3_TILED((k_step3d<16, 2, 2, NC>), 16);
+    case 6: K3_TILED((k_step3d_aligned<8, 4, 1, NC>), 8);
+    case 7: K3_TILED((k_step3d_aligned<16, 2, 1, NC>), 16);
+    case 8: K3_TILED((k_step3d_aligned<4, 5, 1, NC>), 4);
+    case 12: K3_TILED((k_step3d_aligned<8, 2, 2, NC>), 8);
+    case 13: K3_TILED((k_step3d_aligned<8, 3, 2, NC>), 8);
+    case 14: K3_TILED((k_step3d_aligned<16, 1, 2, NC>), 16);
+    case 9: hipLaunchKernelGGL((k_step3d_direct<4, NC>), grid, block, 0, st, A); return true;
+    case 10: hipLaunchKernelGGL((k_step3d_direct<8, NC>), grid, block, 0, st, A); return true;
+    case 11: hipLaunchKernelGGL((k_step3d_direct<16, NC>), grid, block, 0, st, A); return true;
+    default: return false;
+    }
+#undef K3_TILED
+}
+
 at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, int s, int publish)
 {
     if (s != 1) return at_fail(AT_ERR_ARG, "3D stepper advances one step per launch");
@@ -803,27 +864,24 @@ at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, i
     const int TYv = k3_rows(var);
     const int64_t gx = (A.nx + TX - 1) / TX, gy = (A.ny + TYv - 1) / TYv;
     A.ZC = zchunk(A.nz, gx * gy);
-    const bool aligned_var = (var >= 6 && var <= 8) || var >= 12;
-    if (aligned_var && A.ZC > (kZB - 2) * A.Wz) A.ZC = (kZB - 2) * A.Wz;   // LDS delay table
+    if (is_aligned(var) && A.ZC > (kZB - 2) * A.Wz) A.ZC = (kZB - 2) * A.Wz;   // LDS delay table
     const int64_t gz = (A.nz + A.ZC - 1) / A.ZC;
     const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)gz), block(TX, TYv);
     hipStream_t st = at_ctx_stream(ctx);
-    switch (var) {
-    case 0: hipLaunchKernelGGL((k_step3d<8, 1, 4>), grid, block, 0, st, A); break;
-    case 1: hipLaunchKernelGGL((k_step3d<8, 2, 4>), grid, block, 0, st, A); break;
-    case 2: hipLaunchKernelGGL((k_step3d<4, 2, 4>), grid, block, 0, st, A); break;
-    case 3: hipLaunchKernelGGL((k_step3d<4, 2, 3>), grid, block, 0, st, A); break;
-    case 4: hipLaunchKernelGGL((k_step3d<16, 1, 2>), grid, block, 0, st, A); break;
-    case 5: hipLaunchKernelGGL((k_step3d<16, 2, 2>), grid, block, 0, st, A); break;
-    case 6: hipLaunchKernelGGL((k_step3d_aligned<8, 4, 1>), grid, block, 0, st, A); break;
-    case 7: hipLaunchKernelGGL((k_step3d_aligned<16, 2, 1>), grid, block, 0, st, A); break;
-    case 8: hipLaunchKernelGGL((k_step3d_aligned<4, 5, 1>), grid, block, 0, st, A); break;
-    case 12: hipLaunchKernelGGL((k_step3d_aligned<8, 2, 2>), grid, block, 0, st, A); break;
-    case 13: hipLaunchKernelGGL((k_step3d_aligned<8, 3, 2>), grid, block, 0, st, A); break;
-    case 14: hipLaunchKernelGGL((k_step3d_aligned<16, 1, 2>), grid, block, 0, st, A); break;
-    case 9: hipLaunchKernelGGL((k_step3d_direct<4>), grid, block, 0, st, A); break;
-    case 10: hipLaunchKernelGGL((k_step3d_direct<8>), grid, block, 0, st, A); break;
-    default: hipLaunchKernelGGL((k_step3d_direct<16>), grid, block, 0, st, A); break;
+    bool ok = false;
+    switch (A.nc) {
+    case 3: ok = launch3<3>(var, grid, block, st, A); break;
+    case 4: ok = launch3<4>(var, grid, block, st, A); break;
+    case 5: ok = launch3<5>(var, grid, block, st, A); break;
+    case 6: ok = launch3<6>(var, grid, block, st, A); break;
+    case 7: ok = launch3<7>(var, grid, block, st, A); break;
+    default: break;
+    }
+    if (!ok) {
+        char msg[96];
+        snprintf(msg, sizeof msg, "3D kernel variant %d has no build for %d components", var,
+                 (int)A.nc);
+        return at_fail(AT_ERR_ARG, msg);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return at_fail(AT_ERR_HIP, hipGetErrorString(e));

@@ -57,11 +57,36 @@ def _ws(**kw):
     (dict(adv_mode=2), at.AT_ERR_ARG),
     (dict(arith=2), at.AT_ERR_ARG),
     (dict(dim=3, n=(16, 16, 16), p=(2, 2, 2), order=2, arith=1), at.AT_ERR_ARG),
+    (dict(alpha=(0.01,)), at.AT_ERR_ARG),                       # scalars are 3D only
+    (dict(dim=3, n=(16, 16, 16), p=(2, 2, 2), alpha=(0.01, -1.0)), at.AT_ERR_ARG),
+    (dict(dim=3, n=(16, 16, 16), p=(2, 2, 2), alpha=(float("inf"),)), at.AT_ERR_ARG),
 ])
 def test_invalid_configs_rejected(kw, status):
     with pytest.raises(at.AtError) as e:
         _ws(**kw)
     assert e.value.status == status
+
+
+def test_scalar_count_bounds_and_reserved_field():
+    cfg = at.make_config(dim=3, n=(16, 16, 16), p=(2, 2, 2), nu=0.05, dt=1e-4, nsteps_max=4)
+    out = ctypes.c_uint64(0)
+    cfg.nscalars = at.AT_MAX_SCALARS + 1
+    assert at.lib().at_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == at.AT_ERR_ARG
+    cfg.nscalars = 1
+    cfg.reserved1 = 7
+    assert at.lib().at_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == at.AT_ERR_ARG
+    with pytest.raises(ValueError):
+        at.make_config(dim=3, n=(16, 16, 16), p=(2, 2, 2), nu=0.05, dt=1e-4, nsteps_max=4,
+                       alpha=(0.1,) * (at.AT_MAX_SCALARS + 1))
+
+
+def test_scalar_ring_grows_with_components():
+    """The ring stores every component of each block face: (3 + s) / 3 times
+    the velocity-only ring."""
+    def ws(alpha):
+        return _ws(dim=3, n=(32, 32, 32), p=(2, 2, 2), L=3, nsteps_max=1, alpha=alpha)
+    w0, w2 = ws(()), ws((0.01, 0.02))
+    assert w2 > w0
 
 
 def test_workspace_sizes():

@@ -1,0 +1,157 @@
+"""GPU parity of the 3D stepper with passive scalars (section 3.1, the second
+line of Eq. (4)) against the CPU oracle, through the C ABI.
+
+Bar: max|u_gpu - u_oracle| / max|u_oracle| <= 1e-12 over every component
+(velocity and scalars; same operations in the same order, so bit equality is
+expected and reported); delays bit-identical."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1911_05769_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _fields(n, nscal, seed):
+    vel = I.u0_modes3d(n, 6, 3, seed)
+    phi = np.stack([I.u0_modes3d(n, 5, 4, seed + 10 + j)[j % 3] for j in range(nscal)])
+    return np.ascontiguousarray(np.concatenate([vel, phi.reshape((nscal,) + vel.shape[1:])]))
+
+
+CASES = [
+    # name, n (x, y, z), p (x, y, z), L, dist, nu, alpha, nsteps, stale
+    ("n16_p2_s1", (16, 16, 16), (2, 2, 2), 2, 0, 0.05, (0.02,), 41, False),
+    ("n24x16x20_p3x2x2_s2", (24, 16, 20), (3, 2, 2), 3, 0, 0.05, (0.05, 0.0), 30, False),
+    ("n130x18x6_p65x9x3_s3_w2", (130, 18, 6), (65, 9, 3), 2, 1, 0.02, (0.01, 0.03, 0.02), 20,
+     False),
+    ("n64x32x16_p1x2x2_s4", (64, 32, 16), (1, 2, 2), 3, 0, 0.02, (0.02, 0.01, 0.005, 0.04), 25,
+     False),
+    ("n32_p4_s2_stale", (32, 32, 32), (4, 4, 4), 3, 0, 0.02, (0.01, 0.04), 25, True),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_parity_scalars(gpu, case):
+    name, n, p, L, dist, nu, alpha, nst, stale = case
+    log("scalar parity", name)
+    u0 = _fields(n, len(alpha), 5)
+    dt = I.dt_rule(2 * math.pi / max(n), float(np.max(np.abs(u0[:3]))), max((nu,) + alpha))
+    st = gpu.Stepper(dim=3, n=n, p=p, order=2, L=L, nu=nu, dt=dt, nsteps_max=nst, seed=11,
+                     dist=dist, halo_mode=1 if stale else 0, alpha=alpha)
+    assert st.shape == (3 + len(alpha), n[2], n[1], n[0])
+    k = st.delays()
+    assert np.array_equal(k, oracle.delays(nst, 6 * p[0] * p[1] * p[2], L, 2, dist, 11))
+    u, s = dev(u0), torch.empty(u0.shape, dtype=torch.float64, device="cuda")
+    st.run(u, s, nst)
+    got = host(u)
+    ref = oracle.run3d(u0, n, p, L, nu, dt, k, nst, stale=stale, alpha=alpha)
+    assert np.all(np.isfinite(ref))
+    err = relerr(got, ref)
+    log("  rel err %.3e bitwise %s" % (err, np.array_equal(got, ref)))
+    assert err <= TOL
+    for c in range(3 + len(alpha)):
+        assert relerr(got[c], ref[c]) <= TOL, "component %d" % c
+
+
+@pytest.mark.parametrize("nscal", [1, 2, 4])
+def test_every_kernel_variant_scalars(gpu, nscal):
+    """Every kernel variant built for 3 + nscal components gives the oracle's
+    bits; the ones refused are tiled variants whose LDS planes would exceed
+    the 160 KiB of a workgroup."""
+    n, p, L, nu, nst = (128, 64, 48), (2, 4, 3), 3, 0.01, 17
+    alpha = tuple(0.004 * (j + 1) for j in range(nscal))
+    u0 = _fields(n, nscal, 8)
+    dt = I.dt_rule(2 * math.pi / max(n), float(np.max(np.abs(u0[:3]))), max((nu,) + alpha))
+    nc = 3 + nscal
+    outs, k = {}, None
+    for v in range(15):
+        st = gpu.Stepper(dim=3, n=n, p=p, order=2, L=L, nu=nu, dt=dt, nsteps_max=nst, seed=3,
+                         alpha=alpha)
+        try:
+            st.set_variant(v)
+        except gpu.AtError as e:
+            rows = [8, 8, 4, 4, 16, 16, 8, 16, 4, 4, 8, 16, 8, 8, 16][v]
+            assert e.status == gpu.AT_ERR_ARG
+            assert 2 * nc * (rows + 2) * 66 * 8 + 384 > 160 * 1024 and not 9 <= v <= 11
+            continue
+        u, s = dev(u0), torch.empty(u0.shape, dtype=torch.float64, device="cuda")
+        st.run(u, s, nst)
+        outs[v] = host(u)
+        k = st.delays()
+    ref = oracle.run3d(u0, n, p, L, nu, dt, k, nst, alpha=alpha)
+    log("  %d scalars, variants run:" % nscal, sorted(outs))
+    assert {9, 10, 11} <= set(outs)
+    for v, o in outs.items():
+        assert relerr(o, ref) <= TOL, "variant %d" % v
+        assert np.array_equal(o, ref), "variant %d not bitwise" % v
+
+
+def test_full_size_scalars_first_steps(gpu):
+    """512^3, 8^3 blocks of 64^3, L = 3, two scalars (Schmidt numbers 1 and 2):
+    the first 3 steps on the whole grid against the oracle, all 5 components."""
+    wl = I.wl_scalars_3d()
+    nst = 3
+    alpha = wl.extra["alpha"]
+    log("scalars full size", wl.name)
+    st = gpu.Stepper(dim=3, n=wl.n, p=wl.p, order=2, L=wl.L, nu=wl.nu, dt=wl.dt,
+                     nsteps_max=wl.nsteps, seed=wl.seed, dist=wl.dist, alpha=alpha)
+    u = dev(wl.u0)
+    s = torch.empty_like(u)
+    st.run(u, s, nst)
+    k = st.delays()
+    got = host(u)
+    del s, u
+    ref = oracle.run3d(wl.u0, wl.n, wl.p, wl.L, wl.nu, wl.dt, k, nst, alpha=alpha)
+    err = relerr(got, ref)
+    log("  rel err %.3e bitwise %s" % (err, np.array_equal(got, ref)))
+    assert err <= TOL
+
+
+def test_full_size_scalar_copy_of_velocity_all_steps(gpu):
+    """Property at the full size over all 200 steps: a scalar that starts as
+    u_y with alpha = nu obeys u_y's equation, so it stays bitwise equal to
+    u_y; and the velocity equals that of a run without scalars."""
+    wl = I.wl_solenoidal_3d()
+    log("scalars full size, copy property", wl.name)
+    st0 = gpu.Stepper(dim=3, n=wl.n, p=wl.p, order=2, L=wl.L, nu=wl.nu, dt=wl.dt,
+                      nsteps_max=wl.nsteps, seed=wl.seed, dist=wl.dist)
+    u = dev(wl.u0)
+    s = torch.empty_like(u)
+    st0.run(u, s, wl.nsteps)
+    vel = u.clone()
+    del u, s, st0
+    st = gpu.Stepper(dim=3, n=wl.n, p=wl.p, order=2, L=wl.L, nu=wl.nu, dt=wl.dt,
+                     nsteps_max=wl.nsteps, seed=wl.seed, dist=wl.dist, alpha=(wl.nu,))
+    u = torch.empty(st.shape, dtype=torch.float64, device="cuda")
+    u[:3] = dev(wl.u0)
+    u[3] = u[1]
+    s = torch.empty_like(u)
+    st.run(u, s, wl.nsteps)
+    torch.cuda.synchronize()
+    assert bool(torch.equal(u[:3], vel))
+    assert bool(torch.equal(u[3], u[1]))
+    assert bool(torch.isfinite(u).all())
