@@ -65,7 +65,8 @@ typedef enum {
     AT_ERR_DELAY = -3,   /* a delay outside 0..min(L, max(0, n-m+1))       */
     AT_ERR_HIP = -4,     /* a HIP runtime call failed (message kept)       */
     AT_ERR_NOMEM = -5,   /* workspace too small                            */
-    AT_ERR_STATE = -6    /* call not valid in the context's current state  */
+    AT_ERR_STATE = -6,   /* call not valid in the context's current state  */
+    AT_ERR_TIMEOUT = -7  /* a bounded wait of the weakly-synchronous run gave up */
 } at_status;
 
 /* Delay sources and distributions. */
@@ -150,6 +151,31 @@ at_status at_step(at_ctx *ctx, const double *u_in, double *u_out);
  * every s.  Record mode also stores a checkpoint of u every ckpt_every
  * steps, counted from n = 0. */
 at_status at_run(at_ctx *ctx, double *u, double *scratch, int64_t nsteps);
+
+/* Weakly-synchronous run with EMERGENT delays (paper section 5.2, Algorithm 2;
+ * the AT halos of section 2, Eqs. (1)-(2)).  1D only, from step 0, arith 0,
+ * no record mode.  Each tile is one workgroup that advances without any
+ * global barrier: after each step it writes its two edges into the ring and
+ * then announces the level on a per-edge counter (release at device scope);
+ * before step n it reads the neighbours' newest announced level t (acquire)
+ * and uses the delay k = n - min(t, n), waiting only while k would exceed
+ * min(L, max(0, n - m + 1)).  The delays actually used are stored in the
+ * context's delay array in place of the prescribed ones (at_delays_copy
+ * returns them), so at_run-style replay with those delays, or the oracle,
+ * reproduces u exactly.
+ *   u          device double[n0], advanced in place by nsteps steps
+ *   jitter     0: none; J > 0: before each step a tile idles a pseudo-random
+ *              0..J units of about 128 clocks (hash of seed, tile, step),
+ *              emulating uneven arrival
+ *   spin_limit polls of a counter before a wait gives up (<= 0: 2^20)
+ * Requirements: tile width W = 256 * q with q in {1, 2, 4, 8, 16} (q >= 2 for
+ * order 4), and all P tiles resident at once (else AT_ERR_SHAPE: the launch is
+ * cooperative).  Synchronous: returns after the run.  AT_ERR_TIMEOUT if a
+ * wait gave up: every workgroup then leaves early, u and the delays are
+ * undefined and the step count stays 0.  On success the context is at step
+ * nsteps and may continue with at_step / at_run. */
+at_status at_run_ws(at_ctx *ctx, double *u, int64_t nsteps, int32_t jitter, uint64_t seed,
+                    int64_t spin_limit);
 
 /* Choose steps-per-launch s (1D) or the kernel variant (3D) -- nothing that
  * changes results -- by timing `trial_steps` steps from u0 for each

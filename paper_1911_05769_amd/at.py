@@ -20,12 +20,13 @@ LIB_PATH = os.path.join(_HERE, "libat.so")
 
 AT_ABI_VERSION = 3
 AT_MAX_SCALARS = 4
-AT_OK, AT_ERR_ARG, AT_ERR_SHAPE, AT_ERR_DELAY, AT_ERR_HIP, AT_ERR_NOMEM, AT_ERR_STATE = \
-    0, -1, -2, -3, -4, -5, -6
+AT_OK, AT_ERR_ARG, AT_ERR_SHAPE, AT_ERR_DELAY, AT_ERR_HIP, AT_ERR_NOMEM, AT_ERR_STATE, \
+    AT_ERR_TIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
 DELAY_GENERATE, DELAY_HOST = 0, 1
 DIST_UNIFORM, DIST_HALF_ZERO = 0, 1
 STATUS_NAMES = {0: "AT_OK", -1: "AT_ERR_ARG", -2: "AT_ERR_SHAPE", -3: "AT_ERR_DELAY",
-                -4: "AT_ERR_HIP", -5: "AT_ERR_NOMEM", -6: "AT_ERR_STATE"}
+                -4: "AT_ERR_HIP", -5: "AT_ERR_NOMEM", -6: "AT_ERR_STATE",
+                -7: "AT_ERR_TIMEOUT"}
 
 
 class AtError(RuntimeError):
@@ -79,6 +80,8 @@ SIGNATURES = {
     "at_free": (None, [_P]),
     "at_step": (ctypes.c_int, [_P, _P, _P]),
     "at_run": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64]),
+    "at_run_ws": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                                 ctypes.c_int64]),
     "at_autotune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P]),
     "at_set_fuse": (ctypes.c_int, [_P, ctypes.c_int32]),
     "at_set_adjoint_fuse": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -263,6 +266,13 @@ class Stepper:
     def run(self, u: torch.Tensor, scratch: torch.Tensor, nsteps: int):
         _check(lib().at_run(self._ctx, self._f(u, "u"), self._f(scratch, "scratch"),
                             int(nsteps)), "at_run")
+
+    def run_ws(self, u: torch.Tensor, nsteps: int, jitter: int = 0, seed: int = 0,
+               spin_limit: int = 0):
+        """Weakly-synchronous run with emergent delays (see at_run_ws); the
+        delays used are returned afterwards by delays()."""
+        _check(lib().at_run_ws(self._ctx, self._f(u, "u"), int(nsteps), int(jitter),
+                               int(seed) & 0xFFFFFFFFFFFFFFFF, int(spin_limit)), "at_run_ws")
 
     def autotune(self, u0: torch.Tensor, trial_steps: int) -> int:
         t1, t2 = self.empty(), self.empty()

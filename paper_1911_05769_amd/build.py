@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libat.so")
-SOURCES = ["at_api.hip", "at_step1d.hip", "at_adj1d.hip", "at_step3d.hip"]
+SOURCES = ["at_api.hip", "at_step1d.hip", "at_adj1d.hip", "at_step3d.hip", "at_ws1d.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

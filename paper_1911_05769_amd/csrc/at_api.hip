@@ -46,7 +46,8 @@ constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    uint64_t delays = 0, ring = 0, red = 0, ckpt = 0, seg = 0, lam = 0, mu = 0, gnu = 0, total = 0;
+    uint64_t delays = 0, ring = 0, red = 0, sync = 0, ckpt = 0, seg = 0, lam = 0, mu = 0, gnu = 0,
+             total = 0;
     int64_t nckpt = 0, ngnu = 0;
     int R = 0, Rmu = 0;
 };
@@ -188,6 +189,7 @@ struct at_ctx {
     hipStream_t st;
     int8_t *delays;
     double *ring, *red, *ckpt, *seg, *lam, *mu, *gnu;
+    int32_t *sync;   // 1D: edge counters [P][2], then the error flag
     int64_t n;
     int fuse;
     int variant;     // 3D kernel variant (tile rows, prefetch depth, register budget)
@@ -219,6 +221,10 @@ at_status make_layout(const at_config *c, const Derived &d, Layout &L)
     off = align_up(off + 8ull * (uint64_t)L.R * ring_level_doubles(c, d));
     L.red = off;
     off = align_up(off + 8ull * (kRedBlocks * 5 + 16));
+    if (d.dim == 1) {        // edge counters [P][2] and the error flag of the weakly-synchronous run
+        L.sync = off;
+        off = align_up(off + 4ull * (2 * (uint64_t)d.P + 64));
+    }
     if (c->record) {
         L.nckpt = c->nsteps_max / c->ckpt_every + 1;
         L.ckpt = off;
@@ -464,6 +470,7 @@ at_status at_init(const at_config *cfg, at_ctx **out)
     c->delays = (int8_t *)(base + L.delays);
     c->ring = (double *)(base + L.ring);
     c->red = (double *)(base + L.red);
+    c->sync = d.dim == 1 ? (int32_t *)(base + L.sync) : nullptr;
     c->ckpt = cfg->record ? (double *)(base + L.ckpt) : nullptr;
     c->seg = cfg->record ? (double *)(base + L.seg) : nullptr;
     c->lam = cfg->record ? (double *)(base + L.lam) : nullptr;
@@ -595,6 +602,64 @@ at_status at_run(at_ctx *c, double *u, double *scratch, int64_t nsteps)
         left -= s;
     }
     if (cur != u) AT_HIP(launch_copy(u, cur, field_doubles(c), c->st));
+    return AT_OK;
+}
+
+at_status at_run_ws(at_ctx *c, double *u, int64_t nsteps, int32_t jitter, uint64_t seed,
+                    int64_t spin_limit)
+{
+    if (!c || !u) return fail(AT_ERR_ARG, "null argument");
+    if (c->d.dim != 1) return fail(AT_ERR_ARG, "the weakly-synchronous run is 1D");
+    if (c->cfg.record) return fail(AT_ERR_STATE, "the weakly-synchronous run has no record mode");
+    if (c->cfg.arith != 0) return fail(AT_ERR_ARG, "the weakly-synchronous run uses arith 0");
+    if (c->n != 0) return fail(AT_ERR_STATE, "the weakly-synchronous run starts at step 0");
+    if (nsteps < 0 || nsteps > c->cfg.nsteps_max)
+        return fail(AT_ERR_ARG, "nsteps must be in 0..nsteps_max");
+    if (nsteps >= ((int64_t)1 << 31) - 1) return fail(AT_ERR_ARG, "nsteps too large");
+    if (jitter < 0 || jitter > (1 << 20)) return fail(AT_ERR_ARG, "jitter must be in 0..2^20");
+    const Derived &d = c->d;
+    const int nt = ws1d_threads();
+    if (d.W % nt != 0) return fail(AT_ERR_SHAPE, "tile width must be a multiple of %d", nt);
+    const int64_t ppt = d.W / nt;
+    if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8 && ppt != 16)
+        return fail(AT_ERR_SHAPE, "tile width must be %d x 1, 2, 4, 8 or 16", nt);
+    if (ppt < d.h) return fail(AT_ERR_SHAPE, "order 4 needs tile width >= %d", 2 * nt);
+    const bool linear = c->cfg.adv_mode == 1;
+    const int64_t maxt = ws1d_max_tiles(d.order, linear, (int)ppt);
+    if (d.P > maxt)
+        return fail(AT_ERR_SHAPE, "%lld tiles, but at most %lld workgroups can be resident at once",
+                    (long long)d.P, (long long)maxt);
+    if (nsteps == 0) return AT_OK;
+    int32_t *err = c->sync + 2 * d.P;
+    AT_HIP(launch_ws_init(c->sync, 2 * d.P, -1, err, c->st));
+    Ws1D a{};
+    a.u = u;
+    a.ring = c->ring;
+    a.cnt = c->sync;
+    a.err = err;
+    a.delays = c->delays;
+    a.P = d.P;
+    a.W = d.W;
+    a.n0 = 0;
+    a.nsteps = nsteps;
+    a.spin_limit = spin_limit > 0 ? spin_limit : ((int64_t)1 << 20);
+    a.R = c->lay.R;
+    a.L = c->cfg.L;
+    a.stale = c->cfg.halo_mode;
+    a.jitter = jitter;
+    a.seed = seed;
+    a.coef.nu = c->cfg.nu;
+    a.coef.dt = c->cfg.dt;
+    a.coef.c1 = d.c1[0];
+    a.coef.c2 = d.c2[0];
+    a.coef.cadv = c->cfg.adv_speed;
+    AT_HIP(launch_ws1d(a, d.order, linear, (int)ppt, c->st));
+    int32_t herr = 0;
+    AT_HIP(hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, c->st));
+    AT_HIP(hipStreamSynchronize(c->st));
+    if (herr != 0)
+        return fail(AT_ERR_TIMEOUT, "a wait passed the spin limit; u and the delays are undefined");
+    c->n = nsteps;
     return AT_OK;
 }
 

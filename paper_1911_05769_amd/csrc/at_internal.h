@@ -67,6 +67,20 @@ struct AdjF {
     double nu, dt, c1, c2, cadv;
 };
 
+// Weakly-synchronous 1D run (emergent delays): one workgroup per tile.
+struct Ws1D {
+    double *u;                // field, advanced in place: double[N]
+    double *ring;             // edge levels: [R][P][2][h], level n in slot n mod R
+    int32_t *cnt;             // newest announced level per tile edge: [P][2] (-1: none)
+    int32_t *err;             // 0, or 1 once a wait passed the spin limit
+    int8_t *delays;           // delays used, recorded: k[n][2P]
+    int64_t P, W, n0, nsteps;
+    int64_t spin_limit;       // polls of a counter before a wait gives up
+    int32_t R, L, stale, jitter;
+    uint64_t seed;            // idle-time noise
+    Step1D coef;              // nu, dt, c1, c2, cadv of the update
+};
+
 // Neumaier-compensated accumulator used by the reductions.
 struct Acc {
     double s, c;
@@ -116,6 +130,10 @@ int adj1d_points_per_block();
 hipError_t launch_adj1d_fused(const AdjF &a, int order, bool linear, int ppt, int64_t nblocks,
                               size_t lds, hipStream_t st);
 size_t adj1d_fused_lds_bytes(int order, int S, int NT, int L);
+int ws1d_threads();
+int64_t ws1d_max_tiles(int order, bool linear, int ppt);
+hipError_t launch_ws_init(int32_t *cnt, int64_t n, int32_t v, int32_t *err, hipStream_t st);
+hipError_t launch_ws1d(const Ws1D &a, int order, bool linear, int ppt, hipStream_t st);
 hipError_t launch_gnu_final(const double *part, int64_t nparts, double *out, hipStream_t st);
 hipError_t launch_stats(const double *u, int64_t n, double *part, double *out3, hipStream_t st);
 hipError_t launch_loss(const double *u, const double *t, double *lam, int64_t n, double *part,

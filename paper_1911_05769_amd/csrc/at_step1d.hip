@@ -30,6 +30,7 @@
 //     delayed halo reads; levels before n0 come from the ring in HBM;
 //   * every owned tile-edge point of level n is published to ring slot n mod R.
 #include "at_internal.h"
+#include "at_stencil1d.h"
 
 namespace atk {
 
@@ -52,59 +53,6 @@ __device__ __forceinline__ int64_t ring_slot(const Step1D &a, int64_t d)
     if (x < 0) x += a.R;
     if (x >= a.R) x -= a.R;
     return x;
-}
-
-template <bool FMA = false>
-__device__ __forceinline__ double extrap(int kk, bool stale, double v0, double v1, double v2,
-                                         int M)
-{
-    if (stale) return v0;
-    const double dk = (double)kk;
-    const double d1 = v0 - v1;
-    if constexpr (FMA) {
-        if (M == 2) return fma(dk, d1, v0);
-        const double w2 = 0.5 * dk * (dk + 1.0);
-        return fma(w2, d1 - (v1 - v2), fma(dk, d1, v0));
-    }
-    if (M == 2) return v0 + dk * d1;
-    const double w2 = 0.5 * dk * (dk + 1.0);
-    return (v0 + dk * d1) + w2 * (d1 - (v1 - v2));
-}
-
-template <int ORDER, bool LINEAR, bool FMA = false>
-__device__ __forceinline__ double update(const double *nb, double u, const Step1D &a)
-{
-    if constexpr (FMA) {
-        // contracted: u' = u + A2*T2 - (a*A1)*T1 with T1 = D1/c1, T2 = D2/c2
-        double T1, T2;
-        if constexpr (ORDER == 2) {
-            T1 = nb[1] - nb[0];
-            T2 = fma(-2.0, u, nb[1]) + nb[0];
-        } else {
-            T1 = fma(8.0, nb[2] - nb[1], -(nb[3] - nb[0]));
-            T2 = fma(16.0, nb[2] + nb[1], fma(-30.0, u, -(nb[3] + nb[0])));
-        }
-        const double adv = LINEAR ? a.cadv : u;
-        return fma(a.A2, T2, fma(-(adv * a.A1), T1, u));
-    }
-    // Exact order: D1 = (8(r1-l1) - (r2-l2))*c1, D2 = ((16(r1+l1) - 30u) - (r2+l2))*c2
-    // (order 2: D1 = (r1-l1)*c1, D2 = ((r1 - 2u) + l1)*c2), each operation rounded
-    // on its own.  A product by 2, 8 or 16 is exact, so fusing it with the
-    // following add into one fma rounds once where the separate pair also
-    // rounds once: the same bits in one instruction instead of two.
-    double D1, D2;
-    if constexpr (ORDER == 2) {
-        const double l1 = nb[0], r1 = nb[1];
-        D1 = (r1 - l1) * a.c1;
-        D2 = (fma(-2.0, u, r1) + l1) * a.c2;
-    } else {
-        const double l2 = nb[0], l1 = nb[1], r1 = nb[2], r2 = nb[3];
-        D1 = fma(8.0, r1 - l1, -(r2 - l2)) * a.c1;
-        D2 = (fma(16.0, r1 + l1, -(30.0 * u)) - (r2 + l2)) * a.c2;
-    }
-    const double adv = LINEAR ? a.cadv : u;
-    const double F = a.nu * D2 - adv * D1;
-    return u + a.dt * F;
 }
 
 template <int ORDER, bool LINEAR, bool FMA>

@@ -1,0 +1,252 @@
+// Weakly-synchronous 1D stepper of libat.so for gfx950: the delays EMERGE from
+// the progress of the tiles instead of being prescribed.
+//
+// Method (paper section 5.2, Algorithm 2): every tile advances on its own.
+// After computing level n+1 it writes its two edges into the circular buffer
+// ("ring") slot (n+1) mod R and then announces the level through a per-edge
+// counter (the analogue of a notified put: data first, notification after,
+// with release/acquire ordering at device scope).  Before step n a tile reads
+// the newest announced level t of each neighbour edge; the delay is
+// k = n - min(t, n).  A tile waits only while k would exceed the bound the
+// method allows, min(L, max(0, n - m + 1)) (the blocking receive of
+// Algorithm 2, including its start-up synchrony); otherwise it proceeds at
+// once with the AT halo of section 2, Eqs. (1)-(2), built from levels n-k,
+// n-k-1(, n-k-2) of the neighbour's edge.  The delay actually used is stored
+// as k[n][f], so a run can be replayed exactly with prescribed delays.
+//
+// Work decomposition: one workgroup of 256 threads per tile (tile width
+// W = 256 * PPT), PPT consecutive points per thread held in registers for
+// the whole run; h values per side are traded with the neighbouring threads
+// through LDS each step.  Thread 0 receives the left halo and publishes the
+// tile's left edge, thread 255 the right ones.  All tiles must be resident at
+// once (cooperative launch), and every wait is bounded: past the spin limit a
+// workgroup sets the error flag and leaves, and a waiting workgroup that sees
+// the flag leaves too, so every wave reaches the end of the kernel.
+#include "at_internal.h"
+#include "at_stencil1d.h"
+
+namespace atk {
+
+namespace {
+
+constexpr int kWsThreads = 256;
+
+// Pseudo-random idle time before a step (emulated arrival noise): a 32-bit
+// integer mix of (seed, tile, step); any mixer serves, it only spreads the
+// progress of the tiles.
+__device__ __forceinline__ uint32_t ws_mix(uint32_t a, uint32_t b, uint32_t c)
+{
+    uint32_t h = a * 0x9E3779B1u ^ (b + 0x7F4A7C15u) * 0x85EBCA77u ^ (c + 0x165667B1u) * 0xC2B2AE3Du;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    h *= 0x297A2D39u;
+    h ^= h >> 15;
+    return h;
+}
+
+__device__ __forceinline__ int32_t load_acquire(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_release(int32_t *p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int32_t load_relaxed(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until the edge counter announces at least level `need`; returns the
+// newest announced level, or -2 when the spin limit passed or another
+// workgroup raised the error flag (the flag is then set).
+__device__ int32_t ws_wait(const int32_t *cnt, int32_t need, int32_t *err, int64_t spin_limit)
+{
+    int32_t t = load_acquire(cnt);
+    int64_t spins = 0;
+    while (t < need) {
+        if (++spins > spin_limit) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return -2;
+        }
+        if ((spins & 63) == 0 && load_relaxed(err) != 0) return -2;
+        __builtin_amdgcn_s_sleep(1);
+        t = load_acquire(cnt);
+    }
+    return t;
+}
+
+template <int ORDER, bool LINEAR, int PPT>
+__global__ __launch_bounds__(kWsThreads) void k_ws1d(Ws1D A)
+{
+    constexpr int H = ORDER / 2;
+    constexpr int M = ORDER == 2 ? 2 : 3;
+    static_assert(PPT >= H, "a thread holds at least h points");
+    __shared__ double lo[2][kWsThreads][H], hi[2][kWsThreads][H];
+    __shared__ int s_stop;
+    const int t = threadIdx.x;
+    const int64_t P = A.P, b = blockIdx.x;
+    const int64_t bl = b == 0 ? P - 1 : b - 1, br = b + 1 == P ? 0 : b + 1;
+    const int64_t base = b * A.W + (int64_t)t * PPT;
+    const bool stale = A.stale != 0;
+    const int64_t tile2h = 2 * H;
+    double v[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) v[j] = A.u[base + j];
+    if (t == 0) s_stop = 0;
+
+    // edge of tile q, side s (0 left, 1 right), level n: ring slot n mod R
+    auto edge = [&](int64_t n, int64_t q, int s) -> double * {
+        return A.ring + ((n % A.R) * P + q) * tile2h + s * H;
+    };
+    auto publish = [&](int64_t n) {
+        if (t == 0) {
+            double *e = edge(n, b, 0);
+#pragma unroll
+            for (int i = 0; i < H; ++i) e[i] = v[i];
+            store_release(A.cnt + 2 * b + 0, (int32_t)n);
+        }
+        if (t == kWsThreads - 1) {
+            double *e = edge(n, b, 1);
+#pragma unroll
+            for (int i = 0; i < H; ++i) e[i] = v[PPT - H + i];
+            store_release(A.cnt + 2 * b + 1, (int32_t)n);
+        }
+    };
+    // AT halo value i (0 .. h-1, left to right along x) of neighbour tile q's
+    // edge s at delay k for step n
+    auto halo = [&](int64_t n, int k, int64_t q, int s, double (&out)[H]) {
+        const double *e0 = edge(n - k, q, s);
+        if (k == 0 || stale) {
+#pragma unroll
+            for (int i = 0; i < H; ++i) out[i] = e0[i];
+            return;
+        }
+        const double *e1 = edge(n - k - 1, q, s);
+        const double *e2 = M == 3 ? edge(n - k - 2, q, s) : e1;
+#pragma unroll
+        for (int i = 0; i < H; ++i) out[i] = extrap<false>(k, false, e0[i], e1[i], e2[i], M);
+    };
+
+    __syncthreads();                                  // s_stop initialised before any wait
+    publish(A.n0);
+    for (int64_t n = A.n0; n < A.n0 + A.nsteps; ++n) {
+        const int buf = (int)(n & 1);
+        if (A.jitter > 0) {
+            const uint32_t idle = ws_mix((uint32_t)A.seed, (uint32_t)b, (uint32_t)n) %
+                                  (uint32_t)(A.jitter + 1);
+            for (uint32_t i = 0; i < idle; ++i) __builtin_amdgcn_s_sleep(2);
+        }
+        // thread edges for the neighbouring threads
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            lo[buf][t][i] = v[i];
+            hi[buf][t][i] = v[PPT - H + i];
+        }
+        // receive: the newest announced level of the neighbour edge, waiting
+        // only while the delay would pass its bound
+        const int32_t kmax = (int32_t)min((int64_t)A.L, max((int64_t)0, n - M + 1));
+        double hl[H], hr[H];
+        if (t == 0 || t == kWsThreads - 1) {
+            const int s = t == 0 ? 1 : 0;                 // the neighbour's facing edge
+            const int64_t q = t == 0 ? bl : br;
+            const int32_t got = ws_wait(A.cnt + 2 * q + s, (int32_t)(n - kmax), A.err,
+                                        A.spin_limit);
+            if (got == -2) {
+                s_stop = 1;
+            } else {
+                const int k = (int)(n - min((int64_t)got, n));
+                A.delays[n * 2 * P + 2 * b + (t == 0 ? 0 : 1)] = (int8_t)k;
+                if (t == 0) halo(n, k, q, s, hl);
+                else halo(n, k, q, s, hr);
+            }
+        }
+        __syncthreads();
+        if (s_stop) break;
+        // stencil: ext = [left h][own PPT][right h]
+        double ext[PPT + 2 * H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            ext[i] = t == 0 ? hl[i] : hi[buf][t - 1][i];
+            ext[H + PPT + i] = t == kWsThreads - 1 ? hr[i] : lo[buf][t + 1][i];
+        }
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) ext[H + j] = v[j];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            double nb[4];
+            if constexpr (ORDER == 2) {
+                nb[0] = ext[j];
+                nb[1] = ext[j + 2];
+            } else {
+                nb[0] = ext[j];
+                nb[1] = ext[j + 1];
+                nb[2] = ext[j + 3];
+                nb[3] = ext[j + 4];
+            }
+            v[j] = update<ORDER, LINEAR, false>(nb, ext[H + j], A.coef);
+        }
+        publish(n + 1);
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) A.u[base + j] = v[j];
+}
+
+__global__ __launch_bounds__(256) void k_ws_init(int32_t *cnt, int64_t n, int32_t v, int32_t *err)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) cnt[i] = v;
+    if (i == 0) *err = 0;
+}
+
+// the kernel for (order, advection mode, points per thread), or null
+const void *ws1d_kernel(int order, bool linear, int ppt)
+{
+#define WS_PICK(O, PP)                                                                         \
+    if (order == O && ppt == PP)                                                               \
+        return linear ? (const void *)k_ws1d<O, true, PP> : (const void *)k_ws1d<O, false, PP>;
+    WS_PICK(2, 1) WS_PICK(2, 2) WS_PICK(2, 4) WS_PICK(2, 8) WS_PICK(2, 16)
+    WS_PICK(4, 2) WS_PICK(4, 4) WS_PICK(4, 8) WS_PICK(4, 16)
+#undef WS_PICK
+    return nullptr;
+}
+
+}  // namespace
+
+int ws1d_threads() { return kWsThreads; }
+
+// Largest number of k_ws1d workgroups that can be resident at once for this
+// order and points per thread (0 if the variant does not exist)
+int64_t ws1d_max_tiles(int order, bool linear, int ppt)
+{
+    const void *f = ws1d_kernel(order, linear, ppt);
+    if (!f) return 0;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kWsThreads, 0) != hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return (int64_t)per_cu * cus;
+}
+
+hipError_t launch_ws_init(int32_t *cnt, int64_t n, int32_t v, int32_t *err, hipStream_t st)
+{
+    const int64_t g = (n + 255) / 256;
+    hipLaunchKernelGGL(k_ws_init, dim3((unsigned)(g > 0 ? g : 1)), dim3(256), 0, st, cnt, n, v,
+                       err);
+    return hipGetLastError();
+}
+
+hipError_t launch_ws1d(const Ws1D &a, int order, bool linear, int ppt, hipStream_t st)
+{
+    const void *f = ws1d_kernel(order, linear, ppt);
+    if (!f) return hipErrorInvalidValue;
+    void *args[] = {(void *)&a};
+    return hipLaunchCooperativeKernel(f, dim3((unsigned)a.P), dim3(kWsThreads), args, 0, st);
+}
+
+}  // namespace atk

@@ -1,0 +1,165 @@
+"""The weakly-synchronous run with emergent delays (section 5.2, Algorithm 2)
+on the GPU, through the C ABI.
+
+Its delays are not prescribed, so a run has no unique result in advance; it
+is checked afterwards.  The delays it used (read back from the context) must
+obey the method's bounds 0 <= k <= min(L, max(0, n - m + 1)), must grow by at
+most one level per step (the newest announced level never decreases), and
+the oracle replaying exactly those delays must reproduce the GPU field to the
+parity bar (same operations in the same order: bit equality is expected)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1911_05769_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def check_recorded(k, nst, L, m):
+    kk = k[:nst].astype(np.int64)
+    n = np.arange(nst)[:, None]
+    bound = np.minimum(L, np.maximum(0, n - m + 1))
+    assert np.all(kk >= 0) and np.all(kk <= bound), "delay outside its bound"
+    assert np.all(kk[1:] <= kk[:-1] + 1), "delay grew by more than one level in a step"
+    assert oracle.check_delays(k[:nst], L, m)
+    return np.bincount(kk.ravel(), minlength=L + 1)
+
+
+CASES = [
+    # name, N, P, order, L, linear, stale, jitter, nsteps
+    ("o2_P32_q2_jit", 32 * 512, 32, 2, 3, False, False, 60, 300),
+    ("o4_P24_q4_jit", 24 * 1024, 24, 4, 4, False, False, 100, 300),
+    ("o2_linear_P16_q1", 16 * 256, 16, 2, 2, True, False, 40, 400),
+    ("o4_stale_P8_q2", 8 * 512, 8, 4, 3, False, True, 80, 200),
+    ("o2_L0_sync_P64", 64 * 256, 64, 2, 0, False, False, 30, 200),
+    ("o4_P1_q16", 4096, 1, 4, 2, False, False, 0, 200),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_ws_replay_matches_oracle(gpu, case):
+    name, N, P, order, L, linear, stale, jitter, nst = case
+    log("ws replay", name)
+    u0 = I.u0_sines(N, 3)
+    nu = 0.02
+    c = 1.0 if linear else 0.0
+    dt = I.dt_rule(2 * math.pi / N, max(float(np.max(np.abs(u0))), c), nu)
+    st = gpu.Stepper(dim=1, n=N, p=P, order=order, L=L, nu=nu, dt=dt, nsteps_max=nst,
+                     seed=5, halo_mode=1 if stale else 0, adv_mode=1 if linear else 0,
+                     adv_speed=c)
+    u = dev(u0)
+    st.run_ws(u, nst, jitter=jitter, seed=17)
+    got = host(u)
+    k = st.delays()
+    m = oracle.levels_for_order(order)
+    hist = check_recorded(k, nst, L, m)
+    log("  delay histogram", hist.tolist())
+    ref = oracle.run1d(u0, N, P, order, L, nu, dt, k, nst, stale=stale, linear=linear,
+                       adv_speed=c)
+    err = relerr(got, ref)
+    log("  rel err %.3e bitwise %s" % (err, np.array_equal(got, ref)))
+    assert err <= TOL
+    if L == 0:
+        assert hist.sum() == hist[0]
+    if jitter > 0 and L > 0 and P > 1:
+        assert hist[1:].sum() > 0, "uneven progress produced no delay at all"
+
+
+def test_ws_large_replay_and_continue(gpu):
+    """N = 2^20, 1024 tiles of 1024 points, order 2, L = 3: 1000 weakly-
+    synchronous steps, then 200 prescribed steps continuing from the ring
+    the weakly-synchronous run published; the oracle replays all 1200 steps
+    with the recorded-then-prescribed delays."""
+    wl = I.wl_adjoint_1d()
+    N, P, L = wl.n[0], wl.p[0], wl.L
+    nws, npre = 1000, 200
+    st = gpu.Stepper(dim=1, n=N, p=P, order=2, L=L, nu=wl.nu, dt=wl.dt,
+                     nsteps_max=nws + npre, seed=wl.seed, dist=wl.dist)
+    u = dev(wl.u0)
+    s = torch.empty_like(u)
+    st.run_ws(u, nws)
+    st.run(u, s, npre)
+    got = host(u)
+    k = st.delays()
+    hist = check_recorded(k, nws, L, 2)
+    log("  delay histogram (no jitter)", hist.tolist())
+    ref = oracle.run1d(wl.u0, N, P, 2, L, wl.nu, wl.dt, k, nws + npre)
+    err = relerr(got, ref)
+    log("  rel err %.3e bitwise %s" % (err, np.array_equal(got, ref)))
+    assert err <= TOL
+
+
+def test_ws_rejects(gpu):
+    base = dict(dim=1, n=4096, p=16, order=2, L=2, nu=0.02, dt=1e-4, nsteps_max=10, seed=1)
+    u = torch.zeros(4096, dtype=torch.float64, device="cuda")
+
+    def status(**kw):
+        cfg = dict(base)
+        cfg.update(kw)
+        st = gpu.Stepper(**cfg)
+        try:
+            st.run_ws(torch.zeros(st.shape, dtype=torch.float64, device="cuda"), 5)
+        except gpu.AtError as e:
+            return e.status
+        return gpu.AT_OK
+
+    assert status(n=4096, p=32) == gpu.AT_ERR_SHAPE          # W = 128
+    assert status(n=4096 * 3, p=16) == gpu.AT_ERR_SHAPE      # W = 768 (3 x 256)
+    assert status(order=4, n=4096, p=16) == gpu.AT_ERR_SHAPE  # W = 256 < 2 x 256
+    assert status(n=1 << 22, p=1 << 14) == gpu.AT_ERR_SHAPE  # more tiles than resident workgroups
+    assert status(arith=1) == gpu.AT_ERR_ARG
+    assert status(record=True, ckpt_every=5) == gpu.AT_ERR_STATE
+    st = gpu.Stepper(**base)
+    st.run_ws(u, 3)
+    with pytest.raises(gpu.AtError) as e:
+        st.run_ws(u, 3)                                      # not at step 0 any more
+    assert e.value.status == gpu.AT_ERR_STATE
+    st3 = gpu.Stepper(dim=3, n=(16, 16, 16), p=(2, 2, 2), order=2, L=2, nu=0.02, dt=1e-4,
+                      nsteps_max=4, seed=1)
+    with pytest.raises(gpu.AtError) as e:
+        st3.run_ws(torch.zeros(st3.shape, dtype=torch.float64, device="cuda"), 2)
+    assert e.value.status == gpu.AT_ERR_ARG
+
+
+def test_ws_bounded_wait_gives_up(gpu):
+    """A spin limit of one poll with long idle times and L = 0 (every step
+    waits for both neighbours): a wait gives up, every workgroup leaves, the
+    call reports AT_ERR_TIMEOUT, and the device keeps working."""
+    st = gpu.Stepper(dim=1, n=64 * 256, p=64, order=2, L=0, nu=0.02, dt=1e-4, nsteps_max=4,
+                     seed=1)
+    u = torch.zeros(64 * 256, dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu.AtError) as e:
+        st.run_ws(u, 4, jitter=1 << 20, seed=3, spin_limit=1)
+    assert e.value.status == gpu.AT_ERR_TIMEOUT
+    u0 = I.u0_sines(64 * 256, 1)
+    dt = I.dt_rule(2 * math.pi / (64 * 256), float(np.max(np.abs(u0))), 0.02)
+    st2 = gpu.Stepper(dim=1, n=64 * 256, p=64, order=2, L=1, nu=0.02, dt=dt, nsteps_max=4,
+                      seed=1)
+    u2 = dev(u0)
+    st2.run_ws(u2, 4)
+    ref = oracle.run1d(u0, 64 * 256, 64, 2, 1, 0.02, dt, st2.delays(), 4)
+    assert relerr(host(u2), ref) <= TOL
