@@ -211,7 +211,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--only", choices=["main", "all"], default="all")
-    ap.add_argument("--legs", default="plain,contracted,batched,adjoint,3d,scalars",
+    ap.add_argument("--legs", default="plain,contracted,batched,adjoint,3d,scalars,ws",
                     help="comma-separated sub-measurements run with --only all")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fuse", type=int, default=None,
@@ -428,6 +428,58 @@ def bench_adjoint(args, torch, at, I):
             "n": N, "nsteps": nst, "ckpt_every": C}
 
 
+def bench_ws(args, torch, at, I):
+    """Weakly-synchronous runs with emergent delays (one workgroup per tile, no
+    global barrier, per-edge counters): N = 2^20, 1024 tiles of 1024 points,
+    order 2, 2000 steps, L = 3 against L = 0 (every step waits for both
+    neighbours: the synchronous algorithm), and the prescribed-delay path on
+    the same grid (autotuned steps per launch, delays U{0..3})."""
+    import numpy as np
+    wl = I.wl_adjoint_1d()
+    N, P, nst = wl.n[0], wl.p[0], 2000
+    u0 = torch.from_numpy(wl.u0).cuda()
+    out = {"n": N, "p": P, "nsteps": nst}
+    for L in (3, 0):
+        best, hist = None, None
+        for rep in range(max(1, min(args.steps, 3)) + 1):
+            st = at.Stepper(n=N, p=P, order=2, L=L, nu=wl.nu, dt=wl.dt, nsteps_max=nst,
+                            seed=wl.seed)
+            u = u0.clone()
+            tm = Timer(torch)
+            tm.start()
+            st.run_ws(u, nst)
+            tm.stop()
+            ms = tm.total_ms()
+            if rep > 0 and (best is None or ms < best):      # the first run warms up
+                best = ms
+                hist = np.bincount(st.delays()[:nst].ravel().astype(np.int64), minlength=L + 1)
+        frac = (hist / hist.sum()).round(4).tolist()
+        eprint("[ws] L=%d: %.2f ms/run (%.2f us/step), delays k=0..%d: %s" %
+               (L, best, best * 1e3 / nst, L, frac))
+        out["ws_L%d" % L] = {"ms_per_run": round(best, 3), "us_per_step": round(best * 1e3 / nst, 3),
+                             "updates_per_s": N * nst / (best * 1e-3), "delay_fractions": frac}
+    st = at.Stepper(n=N, p=P, order=2, L=3, nu=wl.nu, dt=wl.dt, nsteps_max=nst, seed=wl.seed)
+    fuse = st.autotune(u0, 64)
+    u, s = u0.clone(), torch.empty_like(u0)
+    snap = st.snapshot(u0)
+    st.restore(snap, u)
+    st.run(u, s, nst)
+    tm = Timer(torch)
+    reps = max(1, min(args.steps, 3))
+    for _ in range(reps):
+        st.restore(snap, u)
+        tm.start()
+        st.run(u, s, nst)
+        tm.stop()
+    ms = tm.total_ms() / reps
+    eprint("[ws] prescribed delays, fused s=%d: %.2f ms/run" % (fuse, ms))
+    out["prescribed_L3"] = {"ms_per_run": round(ms, 3), "fuse_steps": fuse,
+                            "updates_per_s": N * nst / (ms * 1e-3)}
+    out["value"] = out["ws_L3"]["updates_per_s"]
+    out["unit"] = "grid-point updates/s (weakly-synchronous, emergent delays)"
+    return out
+
+
 def _bench_3d_run(args, torch, at, wl, alpha, tag):
     """Autotuned kernel variant, then whole runs of wl.nsteps steps timed from a
     restored snapshot; algorithmic bytes per point-update: NC = 3 + scalars
@@ -482,7 +534,7 @@ def bench_scalars(args, torch, at, I):
 
 
 EXTRA = [("batched", bench_batched), ("adjoint", bench_adjoint), ("3d", bench_3d),
-         ("scalars", bench_scalars)]
+         ("scalars", bench_scalars), ("ws", bench_ws)]
 
 if __name__ == "__main__":
     main()

@@ -4,8 +4,9 @@
 // Method (paper section 5.2, Algorithm 2): every tile advances on its own.
 // After computing level n+1 it writes its two edges into the circular buffer
 // ("ring") slot (n+1) mod R and then announces the level through a per-edge
-// counter (the analogue of a notified put: data first, notification after,
-// with release/acquire ordering at device scope).  Before step n a tile reads
+// counter (the analogue of a notified put: data first, notification after;
+// the data moves with device-coherent stores and loads, and the counter is
+// written only once those stores have completed).  Before step n a tile reads
 // the newest announced level t of each neighbour edge; the delay is
 // k = n - min(t, n).  A tile waits only while k would exceed the bound the
 // method allows, min(L, max(0, n - m + 1)) (the blocking receive of
@@ -45,27 +46,46 @@ __device__ __forceinline__ uint32_t ws_mix(uint32_t a, uint32_t b, uint32_t c)
     return h;
 }
 
-__device__ __forceinline__ int32_t load_acquire(const int32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void store_release(int32_t *p, int32_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 __device__ __forceinline__ int32_t load_relaxed(const int32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Ring values move with device-scope (coherent) stores and loads: they write
+// through, and read past, the per-XCD L2, so no cache-wide write-back or
+// invalidate is needed to pass them between workgroups on different XCDs.
+__device__ __forceinline__ void ring_put(double *p, double v)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
+                       (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double ring_get(const double *p)
+{
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED,
+        __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Announce level v on an edge counter: the coherent ring stores issued
+// before it have completed (vmcnt 0) when the counter store is issued, so a
+// reader that sees v and then loads the ring (addresses computed from v)
+// sees the values.
+__device__ __forceinline__ void announce(int32_t *p, int32_t v)
+{
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Wait until the edge counter announces at least level `need`; returns the
 // newest announced level, or -2 when the spin limit passed or another
-// workgroup raised the error flag (the flag is then set).
+// workgroup raised the error flag (the flag is then set).  The polls are
+// relaxed device-scope loads; the ring reads that follow depend on the
+// returned level and are issued after the last poll has returned.
 __device__ int32_t ws_wait(const int32_t *cnt, int32_t need, int32_t *err, int64_t spin_limit)
 {
-    int32_t t = load_acquire(cnt);
+    int32_t t = load_relaxed(cnt);
     int64_t spins = 0;
     while (t < need) {
         if (++spins > spin_limit) {
@@ -74,8 +94,9 @@ __device__ int32_t ws_wait(const int32_t *cnt, int32_t need, int32_t *err, int64
         }
         if ((spins & 63) == 0 && load_relaxed(err) != 0) return -2;
         __builtin_amdgcn_s_sleep(1);
-        t = load_acquire(cnt);
+        t = load_relaxed(cnt);
     }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     return t;
 }
 
@@ -106,14 +127,14 @@ __global__ __launch_bounds__(kWsThreads) void k_ws1d(Ws1D A)
         if (t == 0) {
             double *e = edge(n, b, 0);
 #pragma unroll
-            for (int i = 0; i < H; ++i) e[i] = v[i];
-            store_release(A.cnt + 2 * b + 0, (int32_t)n);
+            for (int i = 0; i < H; ++i) ring_put(e + i, v[i]);
+            announce(A.cnt + 2 * b + 0, (int32_t)n);
         }
         if (t == kWsThreads - 1) {
             double *e = edge(n, b, 1);
 #pragma unroll
-            for (int i = 0; i < H; ++i) e[i] = v[PPT - H + i];
-            store_release(A.cnt + 2 * b + 1, (int32_t)n);
+            for (int i = 0; i < H; ++i) ring_put(e + i, v[PPT - H + i]);
+            announce(A.cnt + 2 * b + 1, (int32_t)n);
         }
     };
     // AT halo value i (0 .. h-1, left to right along x) of neighbour tile q's
@@ -122,13 +143,14 @@ __global__ __launch_bounds__(kWsThreads) void k_ws1d(Ws1D A)
         const double *e0 = edge(n - k, q, s);
         if (k == 0 || stale) {
 #pragma unroll
-            for (int i = 0; i < H; ++i) out[i] = e0[i];
+            for (int i = 0; i < H; ++i) out[i] = ring_get(e0 + i);
             return;
         }
         const double *e1 = edge(n - k - 1, q, s);
         const double *e2 = M == 3 ? edge(n - k - 2, q, s) : e1;
 #pragma unroll
-        for (int i = 0; i < H; ++i) out[i] = extrap<false>(k, false, e0[i], e1[i], e2[i], M);
+        for (int i = 0; i < H; ++i)
+            out[i] = extrap<false>(k, false, ring_get(e0 + i), ring_get(e1 + i), ring_get(e2 + i), M);
     };
 
     __syncthreads();                                  // s_stop initialised before any wait
