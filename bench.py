@@ -31,8 +31,9 @@ METRIC = "grid-point updates/s & % HBM peak (AT step, adjoint, batched) vs plain
 # HBM bytes per launch of the headline kernel (56 fused steps), from rocprofv3
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (scales from a plain 1 GiB copy); only
 # reported while the kernel source is the one the counters were taken on.
-TRAFFIC = {"source": "paper_1911_05769_amd/csrc/at_step1d.hip",
-           "md5": "c837ef4b4d965457760c0f32934972bc", "fuse": 56,
+TRAFFIC = {"sources": ["paper_1911_05769_amd/csrc/at_step1d.hip",
+                       "paper_1911_05769_amd/csrc/at_stencil1d.h"],
+           "md5": "pending", "fuse": 56,
            "bytes_per_launch": (73179.0 * 2.0 + 145294.0) * 1024}
 
 
@@ -83,6 +84,19 @@ class Timer:
         self.torch.cuda.synchronize()
         return sum(a.elapsed_time(b) for a, b in self.pairs)
 
+    def each_ms(self):
+        self.torch.cuda.synchronize()
+        return [a.elapsed_time(b) for a, b in self.pairs]
+
+
+def spread(ms):
+    """median and interquartile range of per-run times (ms)"""
+    import numpy as np
+    q1, med, q3 = np.percentile(np.asarray(ms, dtype=np.float64), [25, 50, 75])
+    return {"runs": len(ms), "median_ms": round(float(med), 4),
+            "iqr_ms": [round(float(q1), 4), round(float(q3), 4)],
+            "min_ms": round(float(min(ms)), 4), "max_ms": round(float(max(ms)), 4)}
+
 
 def bench_c2(args, torch, at, I, fuse=None, label="main", arith=0):
     wl = I.wl_powerlaw_1d()
@@ -112,6 +126,7 @@ def bench_c2(args, torch, at, I, fuse=None, label="main", arith=0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms = tm.total_ms()
+    run_ms = tm.each_ms()
     launches = math.ceil(wl.nsteps / s)
     ms_launch = kern_ms / (args.steps * launches)
     # the last launch of a run may carry fewer steps; use the mean steps per launch
@@ -123,7 +138,7 @@ def bench_c2(args, torch, at, I, fuse=None, label="main", arith=0):
     tflops = flops_launch / (ms_launch * 1e-3) / 1e12
     # issue-rate ceiling for this instruction mix: 39.3 T FP64 instructions/s
     alu_peak = FP64_ADDMUL_PEAK_TFLOPS * fl / ins
-    res = dict(wl=wl, s=s, wall=wall, ms_per_step=wall * 1e3 / args.steps,
+    res = dict(wl=wl, s=s, wall=wall, ms_per_step=wall * 1e3 / args.steps, run_ms=run_ms,
                value=N * wl.nsteps * args.steps / wall, ms_launch=ms_launch, gbps=gbps,
                tflops=tflops, alu_peak=alu_peak, arith=arith, launches=launches,
                bytes_launch=bytes_launch, u0=wl.u0,
@@ -134,12 +149,19 @@ def bench_c2(args, torch, at, I, fuse=None, label="main", arith=0):
     return res
 
 
+def sources_md5(paths):
+    import hashlib
+    h = hashlib.md5()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(r):
     """Counter-measured HBM bytes per launch, or None when they do not apply."""
-    import hashlib
     try:
-        with open(os.path.join(ROOT, TRAFFIC["source"]), "rb") as f:
-            md5 = hashlib.md5(f.read()).hexdigest()
+        md5 = sources_md5(TRAFFIC["sources"])
     except OSError:
         return None
     if md5 != TRAFFIC["md5"] or r["s"] != TRAFFIC["fuse"] or r.get("arith", 0) != 0:
@@ -170,11 +192,39 @@ def cpu_baseline(res):
     t0 = time.perf_counter()
     oracle.run1d(wl.u0, N, P, wl.order, wl.L, wl.nu, wl.dt, k, steps)
     el = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = oracle.max_threads()
     eprint("[cpu] oracle %d steps in %.2f s on %d threads" % (steps, el, cores))
+    # one thread, a shorter sample of the same steps
+    steps1 = max(2, min(steps, int(round(8.0 / max(el * cores / steps, 1e-6)))))
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.run1d(wl.u0, N, P, wl.order, wl.L, wl.nu, wl.dt, k, steps1)
+    el1 = time.perf_counter() - t0
+    oracle.set_threads(cores)
+    eprint("[cpu] oracle %d steps in %.2f s on 1 thread" % (steps1, el1))
     return dict(value=N * steps / el, unit="grid-point updates/s", cores=cores, kind="oracle",
                 sample="first %d of the 2000 steps of the same workload (N=2^24, P=4096, "
-                       "order 4, same u0 and delays), %.1f s wall" % (steps, el))
+                       "order 4, same u0 and delays), %.1f s wall" % (steps, el),
+                value_1thread=N * steps1 / el1, sample_1thread="first %d steps, %.1f s" %
+                (steps1, el1), host=host_info())
+
+
+def host_info():
+    info = {"nproc": os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    info["ram_gb"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return info
 
 
 def copy_ceiling(torch, n=1 << 27, reps=5):
@@ -208,10 +258,10 @@ def calibrate(torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--only", choices=["main", "all"], default="all")
-    ap.add_argument("--legs", default="plain,contracted,batched,adjoint,3d,scalars,ws",
+    ap.add_argument("--legs", default="plain,contracted,c1,batched,adjoint,3d,scalars,ws",
                     help="comma-separated sub-measurements run with --only all")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fuse", type=int, default=None,
@@ -258,6 +308,7 @@ def main():
                    "kernel": "k_step1d_aligned<4,false,false,16>"},
         "roofline": rl,
         "roofline_other": rl_other,
+        "timing": dict(spread(main_res["run_ms"]), clock="HIP events around each 2000-step run"),
     }
     paths = {}
     legs = set(x.strip() for x in args.legs.split(",") if x.strip())
@@ -428,6 +479,43 @@ def bench_adjoint(args, torch, at, I):
             "n": N, "nsteps": nst, "ckpt_every": C}
 
 
+def bench_c1(args, torch, at, I):
+    """The small correctness configuration: N = 1024, P = 8, order 2, L = 2,
+    1000 steps (8 KB of state: launch-latency bound).  Microseconds per step
+    for one launch per step and for the largest steps per launch."""
+    wl = I.wl_sines_1d()
+    N, P = wl.n[0], wl.p[0]
+    u0 = torch.from_numpy(wl.u0).cuda()
+    out = {"workload": wl.name}
+    uT = {}
+    for label, fuse in (("plain", 1), ("fused", 0)):
+        st = at.Stepper(n=N, p=P, order=2, L=wl.L, nu=wl.nu, dt=wl.dt, nsteps_max=wl.nsteps,
+                        seed=wl.seed, dist=wl.dist)
+        if fuse == 0:
+            fuse = st.autotune(u0, 100)
+        else:
+            st.set_fuse(fuse)
+        snap = st.snapshot(u0)
+        u, s = torch.empty_like(u0), torch.empty_like(u0)
+        st.restore(snap, u)
+        st.run(u, s, wl.nsteps)
+        tm = Timer(torch)
+        for _ in range(max(3, args.steps)):
+            st.restore(snap, u)
+            tm.start()
+            st.run(u, s, wl.nsteps)
+            tm.stop()
+        sp = spread(tm.each_ms())
+        uT[label] = u.clone()
+        us = sp["median_ms"] * 1e3 / wl.nsteps
+        eprint("[c1] %s (s=%d): %.3f us/step" % (label, fuse, us))
+        out[label] = {"fuse_steps": fuse, "us_per_step": round(us, 3), "timing": sp}
+    out["bitwise_equal"] = bool(torch.equal(uT["plain"], uT["fused"]))
+    out["value"] = out["fused"]["us_per_step"]
+    out["unit"] = "us/step (lower is better)"
+    return out
+
+
 def bench_ws(args, torch, at, I):
     """Weakly-synchronous runs with emergent delays (one workgroup per tile, no
     global barrier, per-edge counters): N = 2^20, 1024 tiles of 1024 points,
@@ -439,25 +527,30 @@ def bench_ws(args, torch, at, I):
     N, P, nst = wl.n[0], wl.p[0], 2000
     u0 = torch.from_numpy(wl.u0).cuda()
     out = {"n": N, "p": P, "nsteps": nst}
-    for L in (3, 0):
-        best, hist = None, None
-        for rep in range(max(1, min(args.steps, 3)) + 1):
-            st = at.Stepper(n=N, p=P, order=2, L=L, nu=wl.nu, dt=wl.dt, nsteps_max=nst,
-                            seed=wl.seed)
-            u = u0.clone()
-            tm = Timer(torch)
-            tm.start()
-            st.run_ws(u, nst)
-            tm.stop()
-            ms = tm.total_ms()
-            if rep > 0 and (best is None or ms < best):      # the first run warms up
-                best = ms
-                hist = np.bincount(st.delays()[:nst].ravel().astype(np.int64), minlength=L + 1)
-        frac = (hist / hist.sum()).round(4).tolist()
-        eprint("[ws] L=%d: %.2f ms/run (%.2f us/step), delays k=0..%d: %s" %
-               (L, best, best * 1e3 / nst, L, frac))
-        out["ws_L%d" % L] = {"ms_per_run": round(best, 3), "us_per_step": round(best * 1e3 / nst, 3),
-                             "updates_per_s": N * nst / (best * 1e-3), "delay_fractions": frac}
+    # jitter J: before each step a tile idles a pseudo-random 0..J units of
+    # about 128 clocks (uneven arrival, as network noise causes)
+    for jitter in (0, 32):
+        for L in (3, 0):
+            best, hist = None, None
+            for rep in range(max(1, min(args.steps, 3)) + 1):
+                st = at.Stepper(n=N, p=P, order=2, L=L, nu=wl.nu, dt=wl.dt, nsteps_max=nst,
+                                seed=wl.seed)
+                u = u0.clone()
+                tm = Timer(torch)
+                tm.start()
+                st.run_ws(u, nst, jitter=jitter, seed=rep)
+                tm.stop()
+                ms = tm.total_ms()
+                if rep > 0 and (best is None or ms < best):      # the first run warms up
+                    best = ms
+                    hist = np.bincount(st.delays()[:nst].ravel().astype(np.int64),
+                                       minlength=L + 1)
+            frac = (hist / hist.sum()).round(4).tolist()
+            eprint("[ws] jitter %d, L=%d: %.2f ms/run (%.2f us/step), delays k=0..%d: %s" %
+                   (jitter, L, best, best * 1e3 / nst, L, frac))
+            out["ws_L%d_jitter%d" % (L, jitter)] = {
+                "ms_per_run": round(best, 3), "us_per_step": round(best * 1e3 / nst, 3),
+                "updates_per_s": N * nst / (best * 1e-3), "delay_fractions": frac}
     st = at.Stepper(n=N, p=P, order=2, L=3, nu=wl.nu, dt=wl.dt, nsteps_max=nst, seed=wl.seed)
     fuse = st.autotune(u0, 64)
     u, s = u0.clone(), torch.empty_like(u0)
@@ -475,7 +568,7 @@ def bench_ws(args, torch, at, I):
     eprint("[ws] prescribed delays, fused s=%d: %.2f ms/run" % (fuse, ms))
     out["prescribed_L3"] = {"ms_per_run": round(ms, 3), "fuse_steps": fuse,
                             "updates_per_s": N * nst / (ms * 1e-3)}
-    out["value"] = out["ws_L3"]["updates_per_s"]
+    out["value"] = out["ws_L3_jitter0"]["updates_per_s"]
     out["unit"] = "grid-point updates/s (weakly-synchronous, emergent delays)"
     return out
 
@@ -533,8 +626,8 @@ def bench_scalars(args, torch, at, I):
     return _bench_3d_run(args, torch, at, wl, wl.extra["alpha"], "scalars")
 
 
-EXTRA = [("batched", bench_batched), ("adjoint", bench_adjoint), ("3d", bench_3d),
-         ("scalars", bench_scalars), ("ws", bench_ws)]
+EXTRA = [("c1", bench_c1), ("batched", bench_batched), ("adjoint", bench_adjoint),
+         ("3d", bench_3d), ("scalars", bench_scalars), ("ws", bench_ws)]
 
 if __name__ == "__main__":
     main()

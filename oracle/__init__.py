@@ -49,6 +49,10 @@ def lib():
         L.or_run3d.argtypes = [_p, _p, _int, _int, _dbl, _dbl, _dbl, _p, _i64, _p, _p]
         L.or_run3ds.argtypes = [_p, _p, _int, _p, _int, _int, _dbl, _dbl, _dbl, _p, _i64, _p,
                                 _p]
+        L.or_set_threads.argtypes = [_int]
+        L.or_set_threads.restype = None
+        L.or_max_threads.argtypes = []
+        L.or_max_threads.restype = _int
         L.or_stats.argtypes = [_i64, _p, _p]
         L.or_stats.restype = None
         L.or_loss.argtypes = [_i64, _p, _p, _p]
@@ -150,6 +154,15 @@ def run3d(u0, n, p, L, nu, dt, k, nsteps, length=2 * np.pi, stale=False,
                              dt, length, _ptr(k), nsteps, _ptr(u0), _ptr(out))
         _check(st, "or_run3ds")
     return out
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (results do not depend on it)."""
+    lib().or_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().or_max_threads())
 
 
 def stats(u) -> tuple:

@@ -46,6 +46,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_OK 0
 #define OR_ERR_ARG -1
@@ -528,4 +531,24 @@ double or_loss(int64_t n, const double *u, const double *target, double *lam)
         neumaier_add(&s, &c, 0.5 * (d * d));
     }
     return s + c;
+}
+
+/* Threads of the OpenMP loops (timing of the baseline only; the results do
+ * not depend on it: no loop reduces across tiles). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int or_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
