@@ -177,6 +177,11 @@ at_status at_run(at_ctx *ctx, double *u, double *scratch, int64_t nsteps);
 at_status at_run_ws(at_ctx *ctx, double *u, int64_t nsteps, int32_t jitter, uint64_t seed,
                     int64_t spin_limit);
 
+/* The largest tile count P for which at_run_ws can run this context's
+ * configuration on the current device (all tiles resident at once), or 0 when
+ * its tile width is not one at_run_ws supports or the context is not 1D. */
+at_status at_ws_capacity(const at_ctx *ctx, int64_t *max_tiles);
+
 /* Choose steps-per-launch s (1D) or the kernel variant (3D) -- nothing that
  * changes results -- by timing `trial_steps` steps from u0 for each
  * candidate; requires n == 0 and leaves the context at n = 0 with the ring

@@ -82,6 +82,7 @@ SIGNATURES = {
     "at_run": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64]),
     "at_run_ws": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
                                  ctypes.c_int64]),
+    "at_ws_capacity": (ctypes.c_int, [_P, _P]),
     "at_autotune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P]),
     "at_set_fuse": (ctypes.c_int, [_P, ctypes.c_int32]),
     "at_set_adjoint_fuse": (ctypes.c_int, [_P, ctypes.c_int32]),
@@ -273,6 +274,12 @@ class Stepper:
         delays used are returned afterwards by delays()."""
         _check(lib().at_run_ws(self._ctx, self._f(u, "u"), int(nsteps), int(jitter),
                                int(seed) & 0xFFFFFFFFFFFFFFFF, int(spin_limit)), "at_run_ws")
+
+    def ws_capacity(self) -> int:
+        """Largest tile count a weakly-synchronous run of this shape can use."""
+        out = ctypes.c_int64(0)
+        _check(lib().at_ws_capacity(self._ctx, ctypes.byref(out)), "at_ws_capacity")
+        return int(out.value)
 
     def autotune(self, u0: torch.Tensor, trial_steps: int) -> int:
         t1, t2 = self.empty(), self.empty()

@@ -605,6 +605,20 @@ at_status at_run(at_ctx *c, double *u, double *scratch, int64_t nsteps)
     return AT_OK;
 }
 
+at_status at_ws_capacity(const at_ctx *c, int64_t *max_tiles)
+{
+    if (!c || !max_tiles) return fail(AT_ERR_ARG, "null argument");
+    *max_tiles = 0;
+    if (c->d.dim != 1) return AT_OK;
+    const int nt = ws1d_threads();
+    if (c->d.W % nt != 0) return AT_OK;
+    const int64_t ppt = c->d.W / nt;
+    if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8 && ppt != 16) return AT_OK;
+    if (ppt < c->d.h) return AT_OK;
+    *max_tiles = ws1d_max_tiles(c->d.order, c->cfg.adv_mode == 1, (int)ppt);
+    return AT_OK;
+}
+
 at_status at_run_ws(at_ctx *c, double *u, int64_t nsteps, int32_t jitter, uint64_t seed,
                     int64_t spin_limit)
 {

@@ -57,6 +57,9 @@ CASES = [
     ("o4_stale_P8_q2", 8 * 512, 8, 4, 3, False, True, 80, 200),
     ("o2_L0_sync_P64", 64 * 256, 64, 2, 0, False, False, 30, 200),
     ("o4_P1_q16", 4096, 1, 4, 2, False, False, 0, 200),
+    ("o2_P2_q1_L15", 2 * 256, 2, 2, 15, False, False, 200, 300),
+    ("o4_P3_q2_L1_one_step", 3 * 512, 3, 4, 1, False, False, 10, 1),
+    ("o2_P7_q8_L4", 7 * 2048, 7, 2, 4, False, False, 50, 250),
 ]
 
 
@@ -85,7 +88,7 @@ def test_ws_replay_matches_oracle(gpu, case):
     assert err <= TOL
     if L == 0:
         assert hist.sum() == hist[0]
-    if jitter > 0 and L > 0 and P > 1:
+    if jitter > 0 and L > 0 and P > 1 and nst > 50:   # the start-up clamp allows k > 0 from n = m on
         assert hist[1:].sum() > 0, "uneven progress produced no delay at all"
 
 
@@ -163,3 +166,31 @@ def test_ws_bounded_wait_gives_up(gpu):
     st2.run_ws(u2, 4)
     ref = oracle.run1d(u0, 64 * 256, 64, 2, 1, 0.02, dt, st2.delays(), 4)
     assert relerr(host(u2), ref) <= TOL
+
+
+@pytest.mark.parametrize("order,q", [(2, 1), (4, 2), (2, 16)])
+def test_ws_at_resident_capacity(gpu, order, q):
+    """The most tiles the device can keep resident (reported by the library):
+    the run succeeds there and replays exactly; one tile more is refused."""
+    W = 256 * q
+    probe = gpu.Stepper(dim=1, n=W * 8, p=8, order=order, L=2, nu=0.02, dt=1e-5,
+                        nsteps_max=1, seed=1)
+    P = probe.ws_capacity()
+    log("  order %d, W %d: capacity %d tiles" % (order, W, P))
+    assert P >= 256
+    N = P * W
+    u0 = I.u0_sines(N, 4)
+    nst = 60
+    dt = I.dt_rule(2 * math.pi / N, float(np.max(np.abs(u0))), 0.02)
+    st = gpu.Stepper(dim=1, n=N, p=P, order=order, L=2, nu=0.02, dt=dt, nsteps_max=nst, seed=1)
+    u = dev(u0)
+    st.run_ws(u, nst, jitter=8, seed=5)
+    k = st.delays()
+    check_recorded(k, nst, 2, oracle.levels_for_order(order))
+    ref = oracle.run1d(u0, N, P, order, 2, 0.02, dt, k, nst)
+    assert relerr(host(u), ref) <= TOL
+    over = gpu.Stepper(dim=1, n=(P + 1) * W, p=P + 1, order=order, L=2, nu=0.02, dt=dt,
+                       nsteps_max=2, seed=1)
+    with pytest.raises(gpu.AtError) as e:
+        over.run_ws(torch.zeros(over.shape, dtype=torch.float64, device="cuda"), 2)
+    assert e.value.status == gpu.AT_ERR_SHAPE
