@@ -153,33 +153,36 @@ at_status at_step(at_ctx *ctx, const double *u_in, double *u_out);
 at_status at_run(at_ctx *ctx, double *u, double *scratch, int64_t nsteps);
 
 /* Weakly-synchronous run with EMERGENT delays (paper section 5.2, Algorithm 2;
- * the AT halos of section 2, Eqs. (1)-(2)).  1D only, from step 0, arith 0,
- * no record mode.  Each tile is one workgroup that advances without any
- * global barrier: after each step it writes its two edges into the ring and
- * then announces the level on a per-edge counter (release at device scope);
- * before step n it reads the neighbours' newest announced level t (acquire)
- * and uses the delay k = n - min(t, n), waiting only while k would exceed
- * min(L, max(0, n - m + 1)).  The delays actually used are stored in the
- * context's delay array in place of the prescribed ones (at_delays_copy
- * returns them), so at_run-style replay with those delays, or the oracle,
- * reproduces u exactly.
- *   u          device double[n0], advanced in place by nsteps steps
+ * the AT halos of section 2, Eqs. (1)-(2)).  From step 0, arith 0, no record
+ * mode.  Each tile (1D) or block (3D) is one workgroup that advances without
+ * any global barrier: after each step it writes its edges / block faces into
+ * the ring with device-coherent stores and then announces the level on a
+ * counter; before step n it reads the neighbours' newest announced level t
+ * and uses the delay k = n - min(t, n) per face, waiting only while k would
+ * exceed min(L, max(0, n - m + 1)).  The delays actually used are stored in
+ * the context's delay array in place of the prescribed ones (at_delays_copy
+ * returns them), so a replay with those delays (the oracle, or a fresh
+ * context in host-delay mode) reproduces u exactly.
+ *   u          device field, level 0 in, level nsteps out
+ *   scratch    3D: a second device field of the same size (not u); 1D: unused
  *   jitter     0: none; J > 0: before each step a tile idles a pseudo-random
  *              0..J units of about 128 clocks (hash of seed, tile, step),
  *              emulating uneven arrival
  *   spin_limit polls of a counter before a wait gives up (<= 0: 2^20)
- * Requirements: tile width W = 256 * q with q in {1, 2, 4, 8, 16} (q >= 2 for
- * order 4), and all P tiles resident at once (else AT_ERR_SHAPE: the launch is
- * cooperative).  Synchronous: returns after the run.  AT_ERR_TIMEOUT if a
- * wait gave up: every workgroup then leaves early, u and the delays are
- * undefined and the step count stays 0.  On success the context is at step
- * nsteps and may continue with at_step / at_run. */
-at_status at_run_ws(at_ctx *ctx, double *u, int64_t nsteps, int32_t jitter, uint64_t seed,
-                    int64_t spin_limit);
+ * Requirements: 1D: tile width W = 256 * q with q in {1, 2, 4, 8, 16} (q >= 2
+ * for order 4); 3D: block widths multiples of 64 (x) and 8 (y).  All tiles or
+ * blocks must be resident at once (else AT_ERR_SHAPE: the launch is
+ * cooperative; at_ws_capacity gives the limit).  Synchronous: returns after
+ * the run.  AT_ERR_TIMEOUT if a wait gave up: every workgroup then leaves
+ * early, u and the delays are undefined and the step count stays 0.  On
+ * success the context is at step nsteps and may continue with at_step /
+ * at_run. */
+at_status at_run_ws(at_ctx *ctx, double *u, double *scratch, int64_t nsteps, int32_t jitter,
+                    uint64_t seed, int64_t spin_limit);
 
-/* The largest tile count P for which at_run_ws can run this context's
- * configuration on the current device (all tiles resident at once), or 0 when
- * its tile width is not one at_run_ws supports or the context is not 1D. */
+/* The largest tile (1D) or block (3D) count for which at_run_ws can run this
+ * context's configuration on the current device (all resident at once), or 0
+ * when its tile or block shape is not one at_run_ws supports. */
 at_status at_ws_capacity(const at_ctx *ctx, int64_t *max_tiles);
 
 /* Choose steps-per-launch s (1D) or the kernel variant (3D) -- nothing that

@@ -80,7 +80,7 @@ SIGNATURES = {
     "at_free": (None, [_P]),
     "at_step": (ctypes.c_int, [_P, _P, _P]),
     "at_run": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64]),
-    "at_run_ws": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+    "at_run_ws": (ctypes.c_int, [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
                                  ctypes.c_int64]),
     "at_ws_capacity": (ctypes.c_int, [_P, _P]),
     "at_autotune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P]),
@@ -269,10 +269,14 @@ class Stepper:
                             int(nsteps)), "at_run")
 
     def run_ws(self, u: torch.Tensor, nsteps: int, jitter: int = 0, seed: int = 0,
-               spin_limit: int = 0):
+               spin_limit: int = 0, scratch: torch.Tensor = None):
         """Weakly-synchronous run with emergent delays (see at_run_ws); the
-        delays used are returned afterwards by delays()."""
-        _check(lib().at_run_ws(self._ctx, self._f(u, "u"), int(nsteps), int(jitter),
+        delays used are returned afterwards by delays().  3D needs a scratch
+        field (allocated here when not given)."""
+        if self.dim == 3 and scratch is None:
+            scratch = self.empty()
+        scr = self._f(scratch, "scratch") if scratch is not None else None
+        _check(lib().at_run_ws(self._ctx, self._f(u, "u"), scr, int(nsteps), int(jitter),
                                int(seed) & 0xFFFFFFFFFFFFFFFF, int(spin_limit)), "at_run_ws")
 
     def ws_capacity(self) -> int:

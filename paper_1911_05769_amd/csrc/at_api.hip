@@ -173,8 +173,10 @@ int max_fuse_1d(const Derived &d);
 int ring_levels(const at_config *c, const Derived &d)
 {
     // 1D: any steps-per-launch and points-per-thread choice; 3D: a step reads
-    // levels n-L-1 .. n and publishes level n+1
-    const int smax = d.dim == 1 ? kMaxFuse : 2;
+    // levels n-L-1 .. n and publishes level n+1, and in the weakly-synchronous
+    // run a face neighbour up to L steps behind still reads levels down to
+    // n-2L-1 while this block writes level n+1: 2L + m + 2 slots keep them apart
+    const int smax = d.dim == 1 ? kMaxFuse : c->L + 3;
     int64_t R = c->L + d.m - 1 + smax;
     if (c->record) R = std::max<int64_t>(R, c->nsteps_max + 1);
     return (int)R;
@@ -189,7 +191,7 @@ struct at_ctx {
     hipStream_t st;
     int8_t *delays;
     double *ring, *red, *ckpt, *seg, *lam, *mu, *gnu;
-    int32_t *sync;   // 1D: edge counters [P][2], then the error flag
+    int32_t *sync;   // level counters (1D [P][2], 3D [blocks]), then the error flag
     int64_t n;
     int fuse;
     int variant;     // 3D kernel variant (tile rows, prefetch depth, register budget)
@@ -221,10 +223,10 @@ at_status make_layout(const at_config *c, const Derived &d, Layout &L)
     off = align_up(off + 8ull * (uint64_t)L.R * ring_level_doubles(c, d));
     L.red = off;
     off = align_up(off + 8ull * (kRedBlocks * 5 + 16));
-    if (d.dim == 1) {        // edge counters [P][2] and the error flag of the weakly-synchronous run
-        L.sync = off;
-        off = align_up(off + 4ull * (2 * (uint64_t)d.P + 64));
-    }
+    // level counters of the weakly-synchronous run (1D: [P][2] tile edges;
+    // 3D: one per block), then its error flag
+    L.sync = off;
+    off = align_up(off + 4ull * ((d.dim == 1 ? 2 * (uint64_t)d.P : (uint64_t)d.nb) + 64));
     if (c->record) {
         L.nckpt = c->nsteps_max / c->ckpt_every + 1;
         L.ckpt = off;
@@ -332,6 +334,10 @@ at_status at3_publish(at_ctx *c, const double *u, int64_t n);
 int at3_max_fuse(const at_ctx *c);
 int at3_variants();
 bool at3_variant_ok(const at_config *c, int var);
+int64_t at3_ws_capacity(const at_config *c);
+at_status at3_launch_ws(at_ctx *ctx, double *u, double *scratch, int64_t n0, int64_t nsteps,
+                        int32_t *cnt, int32_t *err, int8_t *delays, int32_t jitter, uint64_t seed,
+                        int64_t spin_limit, int *in_scratch);
 
 // accessors used by the 3D translation unit
 extern "C++" {
@@ -470,7 +476,7 @@ at_status at_init(const at_config *cfg, at_ctx **out)
     c->delays = (int8_t *)(base + L.delays);
     c->ring = (double *)(base + L.ring);
     c->red = (double *)(base + L.red);
-    c->sync = d.dim == 1 ? (int32_t *)(base + L.sync) : nullptr;
+    c->sync = (int32_t *)(base + L.sync);
     c->ckpt = cfg->record ? (double *)(base + L.ckpt) : nullptr;
     c->seg = cfg->record ? (double *)(base + L.seg) : nullptr;
     c->lam = cfg->record ? (double *)(base + L.lam) : nullptr;
@@ -609,7 +615,10 @@ at_status at_ws_capacity(const at_ctx *c, int64_t *max_tiles)
 {
     if (!c || !max_tiles) return fail(AT_ERR_ARG, "null argument");
     *max_tiles = 0;
-    if (c->d.dim != 1) return AT_OK;
+    if (c->d.dim == 3) {
+        *max_tiles = at3_ws_capacity(&c->cfg);
+        return AT_OK;
+    }
     const int nt = ws1d_threads();
     if (c->d.W % nt != 0) return AT_OK;
     const int64_t ppt = c->d.W / nt;
@@ -619,11 +628,10 @@ at_status at_ws_capacity(const at_ctx *c, int64_t *max_tiles)
     return AT_OK;
 }
 
-at_status at_run_ws(at_ctx *c, double *u, int64_t nsteps, int32_t jitter, uint64_t seed,
-                    int64_t spin_limit)
+at_status at_run_ws(at_ctx *c, double *u, double *scratch, int64_t nsteps, int32_t jitter,
+                    uint64_t seed, int64_t spin_limit)
 {
     if (!c || !u) return fail(AT_ERR_ARG, "null argument");
-    if (c->d.dim != 1) return fail(AT_ERR_ARG, "the weakly-synchronous run is 1D");
     if (c->cfg.record) return fail(AT_ERR_STATE, "the weakly-synchronous run has no record mode");
     if (c->cfg.arith != 0) return fail(AT_ERR_ARG, "the weakly-synchronous run uses arith 0");
     if (c->n != 0) return fail(AT_ERR_STATE, "the weakly-synchronous run starts at step 0");
@@ -632,6 +640,36 @@ at_status at_run_ws(at_ctx *c, double *u, int64_t nsteps, int32_t jitter, uint64
     if (nsteps >= ((int64_t)1 << 31) - 1) return fail(AT_ERR_ARG, "nsteps too large");
     if (jitter < 0 || jitter > (1 << 20)) return fail(AT_ERR_ARG, "jitter must be in 0..2^20");
     const Derived &d = c->d;
+    const int64_t spins = spin_limit > 0 ? spin_limit : ((int64_t)1 << 20);
+    if (d.dim == 3) {
+        if (!scratch || scratch == u)
+            return fail(AT_ERR_ARG, "the 3D weakly-synchronous run needs a scratch field apart from u");
+        const int64_t Wx = c->cfg.n[0] / c->cfg.p[0], Wy = c->cfg.n[1] / c->cfg.p[1];
+        if (Wx % 64 != 0 || Wy % 8 != 0)
+            return fail(AT_ERR_SHAPE, "3D weakly-synchronous run: block widths must be multiples "
+                                      "of 64 (x) and 8 (y)");
+        const int64_t maxb = at3_ws_capacity(&c->cfg);
+        if (d.nb > maxb)
+            return fail(AT_ERR_SHAPE, "%lld blocks, but at most %lld workgroups can be resident "
+                                      "at once", (long long)d.nb, (long long)maxb);
+        if (nsteps == 0) return AT_OK;
+        int32_t *err = c->sync + d.nb;
+        const at_status sp = at3_publish(c, u, 0);           // level 0's faces, announced below
+        if (sp) return sp;
+        AT_HIP(launch_ws_init(c->sync, d.nb, 0, err, c->st));
+        int in_scratch = 0;
+        const at_status st = at3_launch_ws(c, u, scratch, 0, nsteps, c->sync, err, c->delays,
+                                           jitter, seed, spins, &in_scratch);
+        if (st) return st;
+        if (in_scratch) AT_HIP(launch_copy(u, scratch, field_doubles(c), c->st));
+        int32_t herr = 0;
+        AT_HIP(hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, c->st));
+        AT_HIP(hipStreamSynchronize(c->st));
+        if (herr != 0)
+            return fail(AT_ERR_TIMEOUT, "a wait passed the spin limit; u and the delays are undefined");
+        c->n = nsteps;
+        return AT_OK;
+    }
     const int nt = ws1d_threads();
     if (d.W % nt != 0) return fail(AT_ERR_SHAPE, "tile width must be a multiple of %d", nt);
     const int64_t ppt = d.W / nt;
@@ -656,7 +694,7 @@ at_status at_run_ws(at_ctx *c, double *u, int64_t nsteps, int32_t jitter, uint64
     a.W = d.W;
     a.n0 = 0;
     a.nsteps = nsteps;
-    a.spin_limit = spin_limit > 0 ? spin_limit : ((int64_t)1 << 20);
+    a.spin_limit = spins;
     a.R = c->lay.R;
     a.L = c->cfg.L;
     a.stale = c->cfg.halo_mode;

@@ -29,6 +29,7 @@
 // width >= 2).
 #include "../../include/at.h"
 #include "at_internal.h"
+#include "at_ws.h"
 
 at_status at_fail(at_status st, const char *msg);
 struct at_ctx;
@@ -274,7 +275,24 @@ struct NbC {
     int k;
 };
 
-template <int NC>
+// Device-coherent load and store of a double (they read past, and write
+// through, the per-XCD L2): how the weakly-synchronous run moves ring values
+// between workgroups that may sit on different XCDs.
+__device__ __forceinline__ double ld_coherent(const double *p)
+{
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED,
+        __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__device__ __forceinline__ void st_coherent(double *p, double v)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
+                       (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int NC, bool COH = false>
 __device__ __forceinline__ NbC<NC> load_nbc(const double *ring, const double *field, bool face,
                                             int k, bool stale, int64_t oring0, int64_t oring1,
                                             int64_t cring, int64_t ofield, int64_t cfield)
@@ -285,9 +303,9 @@ __device__ __forceinline__ NbC<NC> load_nbc(const double *ring, const double *fi
     NbC<NC> r;
     r.k = k;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) r.a[c] = p0[c * cs];
+    for (int c = 0; c < NC; ++c) r.a[c] = COH ? ld_coherent(p0 + c * cs) : p0[c * cs];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) r.b[c] = p1[c * cs];
+    for (int c = 0; c < NC; ++c) r.b[c] = COH ? ld_coherent(p1 + c * cs) : p1[c * cs];
     return r;
 }
 
@@ -307,17 +325,24 @@ __device__ __forceinline__ double at_h(int k, bool stale, double v0, double v1)
 // the same branch-free stencil (the split of section 5.2).  The face delays
 // of the chunk are copied to LDS first, and every load inside the march is
 // consumed one plane after it is issued.
-template <int TY, int MINW, int PF, int NC>
-__global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d_aligned(Step3D A)
+//
+// The march of one 64 x TY tile (corner X0, Y0) through planes Z0 .. Z1-1,
+// reading level n from U0 and writing level n+1 to uout; sl0 is the ring slot
+// of level n, kdl the LDS delay table of the z-blocks from bz0 on (6 per
+// z-block; the prescribed form fills it here from the delay array).  WS (the weakly-synchronous run): ring values move with
+// device-coherent loads and stores, and the z neighbour across a block face
+// comes from the ring whatever k is (the neighbour block's field may already
+// hold another level).
+template <int TY, int PF, int NC, bool WS>
+__device__ __forceinline__ void march3d(const Step3D &A, const double *const U0,
+                                        double *const uout, const int sl0,
+                                        double (*pl)[NC][TY + 2][TX + 2], int8_t *kdl,
+                                        const int X0, const int Y0, const int Z0, const int Z1,
+                                        const int bz0)
 {
     static_assert(PF == 1 || PF == 2, "plane queue of 2 or 3 slots");
-    __shared__ double pl[2][NC][TY + 2][TX + 2];
-    __shared__ int8_t kdl[6 * kZB];
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int nx = (int)A.nx, ny = (int)A.ny, nz = (int)A.nz;
-    const int X0 = blockIdx.x * TX, Y0 = blockIdx.y * TY;
-    const int Z0 = blockIdx.z * A.ZC;
-    const int Z1 = (Z0 + A.ZC < nz) ? Z0 + A.ZC : nz;
     const int x = X0 + tx, y = Y0 + ty;
     const int plane = nx * ny;
     const int col = y * nx + x;
@@ -326,16 +351,11 @@ __global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d_aligned
     const int lx = x - bx * Wx, ly = y - by * Wy;
     const bool fxl = X0 % Wx == 0, fxh = (X0 + TX) % Wx == 0;    // tile edges on block faces
     const bool fyl = Y0 % Wy == 0, fyh = (Y0 + TY) % Wy == 0;
-    const double *const U0 = A.uin;
     const int64_t npt = A.npt;
     const bool stale = A.stale != 0;
-    const int sl0 = A.slot0;
     const int64_t Py = A.Py, Px = A.Px, bstride = A.bstride, level = A.level;
     const int R = A.R;
-
-    // face delays of the z-blocks of this chunk
-    const int bz0 = Z0 / Wz;
-    {
+    if (!WS) {   // face delays of the z-blocks of this chunk (the WS caller fills kdl itself)
         const int nzb = (Z1 - 1) / Wz - bz0 + 1;          // <= kZB (host bounds ZC)
         const int t = ty * TX + tx;
         const int8_t *krow = A.delays + A.n * A.F;
@@ -416,8 +436,8 @@ __global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d_aligned
             const int k = r_face ? kdl[6 * (bz - bz0) + r_fidx] : 0;
             const int64_t off = (r_blk + (int64_t)bz * PyPx) * bstride + r_foff +
                                 (int64_t)lz * r_lzmul + r_pos;
-            rr = load_nbc<NC>(A.ring, U0, r_face, k, stale, lvl(k) + off, lvl(k + 1) + off,
-                              r_cring, (int64_t)p * plane + r_field, npt);
+            rr = load_nbc<NC, WS>(A.ring, U0, r_face, k, stale, lvl(k) + off, lvl(k + 1) + off,
+                                  r_cring, (int64_t)p * plane + r_field, npt);
         }
     };
     // plane p's rim values into LDS buffer bf
@@ -432,17 +452,19 @@ __global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d_aligned
     // loads issued at the start of the step before, consumed at its end
     NbC<NC> zr{};
     int zside = 0;
+    bool zface = false;
     auto issue_z = [&](int p) {
         const int bz = p / Wz, lz = p - bz * Wz;
         zside = lz == 0 ? 0 : 1;
-        const int k = (lz == 0 || lz == Wz - 1) ? kdl[6 * (bz - bz0) + 4 + zside] : 0;
+        zface = lz == 0 || lz == Wz - 1;
+        const int k = zface ? kdl[6 * (bz - bz0) + 4 + zside] : 0;
         zr.k = k;
-        if (k > 0) {
+        if (k > 0 || (WS && zface)) {
             const int nbz = wrap32(bz + (zside ? 1 : -1), A.Pz);
             const int64_t off = (z_blk + (int64_t)nbz * PyPx) * bstride +
                                 (zside ? zhi_foff : zlo_foff) + ly * Wx + lx;
-            zr = load_nbc<NC>(A.ring, U0, true, k, stale, lvl(k) + off, lvl(k + 1) + off, psz2, 0,
-                              npt);
+            zr = load_nbc<NC, WS>(A.ring, U0, true, k, stale, lvl(k) + off, lvl(k + 1) + off, psz2,
+                                  0, npt);
         }
     };
 
@@ -452,7 +474,7 @@ __global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d_aligned
     bool hz_lo = false, hz_hi = false;      // plane's z neighbour replaced by hz (low / high)
     auto take_z = [&]() {
         hz_lo = hz_hi = false;
-        if (zr.k > 0) {
+        if (zr.k > 0 || (WS && zface)) {
 #pragma unroll
             for (int c = 0; c < NC; ++c) hz[c] = at_h(zr.k, stale, zr.a[c], zr.b[c]);
             hz_lo = zside == 0;
@@ -466,7 +488,7 @@ __global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d_aligned
     finish_rims(0);
     take_z();
     if (Z0 + 1 < Z1) issue(Z0 + 1);
-    const int64_t slot = A.slot0 + 1 == A.R ? 0 : A.slot0 + 1;   // level n+1 is published
+    const int64_t slot = sl0 + 1 == A.R ? 0 : sl0 + 1;   // level n+1 is published
     const double c10 = A.c1[0], c11 = A.c1[1], c12 = A.c1[2];
     const double c20 = A.c2[0], c21 = A.c2[1], c22 = A.c2[2];
     const double dt = A.dt;
@@ -485,7 +507,7 @@ __global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d_aligned
         if (more) issue_z(z + 1);
         __syncthreads();
         const double ux = zc[0], uy = zc[1], uz = zc[2];
-        double *out = A.uout + (int64_t)z * plane + col;
+        double *out = uout + (int64_t)z * plane + col;
         double ov[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -512,12 +534,21 @@ __global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d_aligned
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 const double u = ov[c];
-                if (lx == 0) base[A.foff[0] + c * psz0 + px] = u;
-                if (lx == Wx - 1) base[A.foff[1] + c * psz0 + px] = u;
-                if (ly == 0) base[A.foff[2] + c * psz1 + py] = u;
-                if (ly == Wy - 1) base[A.foff[3] + c * psz1 + py] = u;
-                if (lz == 0) base[A.foff[4] + c * psz2 + pz] = u;
-                if (lz == Wz - 1) base[A.foff[5] + c * psz2 + pz] = u;
+                if constexpr (WS) {
+                    if (lx == 0) st_coherent(&base[A.foff[0] + c * psz0 + px], u);
+                    if (lx == Wx - 1) st_coherent(&base[A.foff[1] + c * psz0 + px], u);
+                    if (ly == 0) st_coherent(&base[A.foff[2] + c * psz1 + py], u);
+                    if (ly == Wy - 1) st_coherent(&base[A.foff[3] + c * psz1 + py], u);
+                    if (lz == 0) st_coherent(&base[A.foff[4] + c * psz2 + pz], u);
+                    if (lz == Wz - 1) st_coherent(&base[A.foff[5] + c * psz2 + pz], u);
+                } else {
+                    if (lx == 0) base[A.foff[0] + c * psz0 + px] = u;
+                    if (lx == Wx - 1) base[A.foff[1] + c * psz0 + px] = u;
+                    if (ly == 0) base[A.foff[2] + c * psz1 + py] = u;
+                    if (ly == Wy - 1) base[A.foff[3] + c * psz1 + py] = u;
+                    if (lz == 0) base[A.foff[4] + c * psz2 + pz] = u;
+                    if (lz == Wz - 1) base[A.foff[5] + c * psz2 + pz] = u;
+                }
             }
         }
         if (more) {
@@ -547,6 +578,94 @@ __global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d_aligned
         }
         if (z < Z1) body(z++, qa, qc);
         if (z < Z1) body(z, qb, qa);
+    }
+}
+
+template <int TY, int MINW, int PF, int NC>
+__global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d_aligned(Step3D A)
+{
+    __shared__ double pl[2][NC][TY + 2][TX + 2];
+    __shared__ int8_t kdl[6 * kZB];
+    const int X0 = blockIdx.x * TX, Y0 = blockIdx.y * TY;
+    const int Z0 = blockIdx.z * A.ZC;
+    const int Z1 = (Z0 + A.ZC < (int)A.nz) ? Z0 + A.ZC : (int)A.nz;
+    const int bz0 = Z0 / A.Wz;
+    march3d<TY, PF, NC, false>(A, A.uin, A.uout, A.slot0, pl, kdl, X0, Y0, Z0, Z1, bz0);
+}
+
+// Weakly-synchronous 3D run (emergent delays; paper section 5.2, Algorithm 2):
+// one workgroup per block, all blocks resident at once (cooperative launch).
+// Before step n, lanes 0..5 poll the level counters of the six face
+// neighbours; face f then uses the delay k = n - min(t_f, n), waiting only
+// while k would exceed min(L, max(0, n - 1)), and records it.  The block
+// marches its tiles through level n (ring reads device-coherent), publishes
+// level n+1's faces with device-coherent stores during the march, and
+// announces n+1 on its own counter once every store has completed.  Every
+// wait is bounded (spin limit, error flag), so every wave reaches the end.
+struct Ws3D {
+    int32_t *cnt;             // newest announced level per block: [nb]
+    int32_t *err;             // 0, or 1 once a wait passed the spin limit
+    int8_t *delays;           // delays used, recorded: k[n][6 nb]
+    int64_t n0, nsteps, spin_limit;
+    int32_t L, jitter;
+    uint64_t seed;
+};
+
+constexpr int kWsTY = 8;      // tile rows of the weakly-synchronous 3D kernel
+
+template <int NC>
+__global__ __launch_bounds__(TX * kWsTY, 4) void k_ws3d(Step3D A, Ws3D W)
+{
+    __shared__ double pl[2][NC][kWsTY + 2][TX + 2];
+    __shared__ int8_t kdl[6];
+    __shared__ int s_stop;
+    const int t = threadIdx.y * TX + threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int bx = (int)(b % A.Px), by = (int)((b / A.Px) % A.Py);
+    const int bz = (int)(b / ((int64_t)A.Px * A.Py));
+    int64_t q = b;                                    // lanes 0..5: the neighbour across face t
+    if (t < 6) {
+        const int a = t >> 1, sd = t & 1;
+        int nbx = bx, nby = by, nbz = bz;
+        if (a == 0) nbx = wrap32(bx + (sd ? 1 : -1), A.Px);
+        else if (a == 1) nby = wrap32(by + (sd ? 1 : -1), A.Py);
+        else nbz = wrap32(bz + (sd ? 1 : -1), A.Pz);
+        q = ((int64_t)nbz * A.Py + nby) * A.Px + nbx;
+    }
+    if (t == 0) s_stop = 0;
+    __syncthreads();
+    const double *cur = A.uin;
+    double *nxt = A.uout;
+    const int ntx = A.Wx / TX, nty = A.Wy / kWsTY;
+    for (int64_t n = W.n0; n < W.n0 + W.nsteps; ++n) {
+        ws_idle(W.jitter, W.seed, b, n);
+        if (t < 6) {
+            const int64_t kmax = min((int64_t)W.L, max((int64_t)0, n - 1));
+            const int32_t got = ws_wait(W.cnt + q, (int32_t)(n - kmax), W.err, W.spin_limit);
+            if (got == -2) {
+                s_stop = 1;
+            } else {
+                const int k = (int)(n - min((int64_t)got, n));
+                kdl[t] = (int8_t)k;
+                W.delays[n * A.F + 6 * b + t] = (int8_t)k;
+            }
+        }
+        __syncthreads();
+        if (s_stop) break;
+        const int sl0 = (int)(n % A.R);
+        for (int i = 0; i < ntx; ++i)
+            for (int j = 0; j < nty; ++j)
+                march3d<kWsTY, 1, NC, true>(A, cur, nxt, sl0, pl, kdl, bx * A.Wx + i * TX,
+                                            by * A.Wy + j * kWsTY, bz * A.Wz, bz * A.Wz + A.Wz,
+                                            bz);
+        __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();                              // every face store of level n+1 completed
+        if (t == 0)
+            __hip_atomic_store(W.cnt + b, (int32_t)(n + 1), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        const double *was = cur;
+        cur = nxt;
+        nxt = const_cast<double *>(was);
     }
 }
 
@@ -807,6 +926,65 @@ static void fill_step3d(at_ctx *ctx, const double *uin, double *uout, int64_t n0
     A.dt = c->dt;
     A.ZC = 0;
     at_ctx_coefs(ctx, A.c1, A.c2);
+}
+
+// the k_ws3d build for NC components, or null
+static const void *ws3d_kernel(int nc)
+{
+    switch (nc) {
+    case 3: return (const void *)k_ws3d<3>;
+    case 4: return (const void *)k_ws3d<4>;
+    case 5: return (const void *)k_ws3d<5>;
+    case 6: return (const void *)k_ws3d<6>;
+    case 7: return (const void *)k_ws3d<7>;
+    default: return nullptr;
+    }
+}
+
+// blocks the weakly-synchronous 3D run can keep resident for this
+// configuration, 0 when its block shape is not supported
+int64_t at3_ws_capacity(const at_config *c)
+{
+    const int64_t Wx = c->n[0] / c->p[0], Wy = c->n[1] / c->p[1];
+    if (Wx % TX != 0 || Wy % kWsTY != 0) return 0;
+    const void *f = ws3d_kernel(ncomp(c));
+    if (!f) return 0;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, TX * kWsTY, 0) != hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return (int64_t)per_cu * cus;
+}
+
+// the weakly-synchronous run: level n0 in u, scratch the second field buffer;
+// on return the last level is in u (or in scratch: *in_scratch = 1)
+at_status at3_launch_ws(at_ctx *ctx, double *u, double *scratch, int64_t n0, int64_t nsteps,
+                        int32_t *cnt, int32_t *err, int8_t *delays, int32_t jitter, uint64_t seed,
+                        int64_t spin_limit, int *in_scratch)
+{
+    Step3D A;
+    fill_step3d(ctx, u, scratch, n0, 1, A);
+    const void *f = ws3d_kernel(A.nc);
+    if (!f) return at_fail(AT_ERR_ARG, "no weakly-synchronous 3D build for this component count");
+    Ws3D W;
+    W.cnt = cnt;
+    W.err = err;
+    W.delays = delays;
+    W.n0 = n0;
+    W.nsteps = nsteps;
+    W.spin_limit = spin_limit;
+    W.L = at_ctx_cfg(ctx)->L;
+    W.jitter = jitter;
+    W.seed = seed;
+    void *args[] = {(void *)&A, (void *)&W};
+    const int64_t nb = (int64_t)A.Px * A.Py * A.Pz;
+    hipError_t e = hipLaunchCooperativeKernel(f, dim3((unsigned)nb), dim3(TX, kWsTY), args, 0,
+                                              at_ctx_stream(ctx));
+    if (e != hipSuccess) return at_fail(AT_ERR_HIP, hipGetErrorString(e));
+    *in_scratch = (int)(nsteps & 1);
+    return AT_OK;
 }
 
 at_status at3_publish(at_ctx *ctx, const double *u, int64_t n)

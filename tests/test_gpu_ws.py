@@ -1,5 +1,5 @@
 """The weakly-synchronous run with emergent delays (section 5.2, Algorithm 2)
-on the GPU, through the C ABI.
+on the GPU, through the C ABI, in 1D and 3D.
 
 Its delays are not prescribed, so a run has no unique result in advance; it
 is checked afterwards.  The delays it used (read back from the context) must
@@ -141,11 +141,6 @@ def test_ws_rejects(gpu):
     with pytest.raises(gpu.AtError) as e:
         st.run_ws(u, 3)                                      # not at step 0 any more
     assert e.value.status == gpu.AT_ERR_STATE
-    st3 = gpu.Stepper(dim=3, n=(16, 16, 16), p=(2, 2, 2), order=2, L=2, nu=0.02, dt=1e-4,
-                      nsteps_max=4, seed=1)
-    with pytest.raises(gpu.AtError) as e:
-        st3.run_ws(torch.zeros(st3.shape, dtype=torch.float64, device="cuda"), 2)
-    assert e.value.status == gpu.AT_ERR_ARG
 
 
 def test_ws_bounded_wait_gives_up(gpu):
@@ -194,3 +189,106 @@ def test_ws_at_resident_capacity(gpu, order, q):
     with pytest.raises(gpu.AtError) as e:
         over.run_ws(torch.zeros(over.shape, dtype=torch.float64, device="cuda"), 2)
     assert e.value.status == gpu.AT_ERR_SHAPE
+
+
+# ------------------------------------------------------------------- 3D
+
+CASES3 = [
+    # name, n (x, y, z), p (x, y, z), L, stale, jitter, nsteps, alpha
+    ("n64x32x32_p1x2x2_L2_jit", (64, 32, 32), (1, 2, 2), 2, False, 20, 30, ()),
+    ("n128x64x48_p2x4x3_L3", (128, 64, 48), (2, 4, 3), 3, False, 0, 20, ()),
+    ("n128x16x16_p1x1x2_L3_wide", (128, 16, 16), (1, 1, 2), 3, False, 10, 25, ()),
+    ("n64x32x32_p1x4x2_stale", (64, 32, 32), (1, 4, 2), 3, True, 10, 20, ()),
+    ("n64x16x16_p1x2x2_scalar", (64, 16, 16), (1, 2, 2), 1, False, 10, 20, (0.02,)),
+    ("n64x32x32_p1x2x2_L0", (64, 32, 32), (1, 2, 2), 0, False, 10, 15, ()),
+]
+
+
+def _field3(n, nscal, seed):
+    vel = I.u0_modes3d(n, 6, 3, seed)
+    if not nscal:
+        return vel
+    phi = np.stack([I.u0_modes3d(n, 5, 4, seed + 10 + j)[j % 3] for j in range(nscal)])
+    return np.ascontiguousarray(np.concatenate([vel, phi]))
+
+
+@pytest.mark.parametrize("case", CASES3, ids=[c[0] for c in CASES3])
+def test_ws3d_replay_matches_oracle(gpu, case):
+    name, n, p, L, stale, jitter, nst, alpha = case
+    log("ws3d replay", name)
+    nu = 0.02
+    u0 = _field3(n, len(alpha), 6)
+    dt = I.dt_rule(2 * math.pi / max(n), float(np.max(np.abs(u0[:3]))), max((nu,) + alpha))
+    st = gpu.Stepper(dim=3, n=n, p=p, order=2, L=L, nu=nu, dt=dt, nsteps_max=nst, seed=5,
+                     halo_mode=1 if stale else 0, alpha=alpha)
+    u = dev(u0)
+    st.run_ws(u, nst, jitter=jitter, seed=11)
+    got = host(u)
+    k = st.delays()
+    hist = check_recorded(k, nst, L, 2)
+    log("  delay histogram", hist.tolist())
+    ref = oracle.run3d(u0, n, p, L, nu, dt, k, nst, stale=stale, alpha=alpha)
+    err = relerr(got, ref)
+    log("  rel err %.3e bitwise %s" % (err, np.array_equal(got, ref)))
+    assert err <= TOL
+    if L == 0:
+        assert hist.sum() == hist[0]
+
+
+def test_ws3d_full_size_replay_and_prescribed_equal(gpu):
+    """512^3 x 3, 8^3 blocks of 64^3 (one resident workgroup per block), L = 3:
+    the first 3 weakly-synchronous steps against the oracle on the whole grid;
+    then all 200 steps, and a prescribed-delay run fed the recorded delays
+    (host-delay mode) gives the same bits."""
+    wl = I.wl_solenoidal_3d()
+    st = gpu.Stepper(dim=3, n=wl.n, p=wl.p, order=2, L=wl.L, nu=wl.nu, dt=wl.dt,
+                     nsteps_max=3, seed=wl.seed)
+    cap = st.ws_capacity()
+    log("  capacity %d blocks" % cap)
+    assert cap >= 512
+    u = dev(wl.u0)
+    st.run_ws(u, 3, jitter=4, seed=1)
+    k = st.delays()
+    got = host(u)
+    del u
+    ref = oracle.run3d(wl.u0, wl.n, wl.p, wl.L, wl.nu, wl.dt, k, 3)
+    err = relerr(got, ref)
+    log("  3 steps rel err %.3e bitwise %s" % (err, np.array_equal(got, ref)))
+    assert err <= TOL
+    del got, ref
+    st = gpu.Stepper(dim=3, n=wl.n, p=wl.p, order=2, L=wl.L, nu=wl.nu, dt=wl.dt,
+                     nsteps_max=wl.nsteps, seed=wl.seed)
+    u = dev(wl.u0)
+    s = torch.empty_like(u)
+    st.run_ws(u, wl.nsteps, scratch=s)
+    k = st.delays()
+    hist = check_recorded(k, wl.nsteps, wl.L, 2)
+    log("  200 steps, delay histogram", hist.tolist())
+    rep = gpu.Stepper(dim=3, n=wl.n, p=wl.p, order=2, L=wl.L, nu=wl.nu, dt=wl.dt,
+                      nsteps_max=wl.nsteps, delays=k)
+    rep.set_variant(7)
+    v = dev(wl.u0)
+    rep.run(v, s, wl.nsteps)
+    torch.cuda.synchronize()
+    assert bool(torch.equal(u, v))
+    assert bool(torch.isfinite(u).all())
+
+
+def test_ws3d_rejects(gpu):
+    st = gpu.Stepper(dim=3, n=(32, 32, 32), p=(1, 2, 2), order=2, L=2, nu=0.02, dt=1e-4,
+                     nsteps_max=4, seed=1)
+    assert st.ws_capacity() == 0                         # block width 32 in x
+    with pytest.raises(gpu.AtError) as e:
+        st.run_ws(torch.zeros(st.shape, dtype=torch.float64, device="cuda"), 2)
+    assert e.value.status == gpu.AT_ERR_SHAPE
+    st = gpu.Stepper(dim=3, n=(64, 20, 16), p=(1, 2, 2), order=2, L=2, nu=0.02, dt=1e-4,
+                     nsteps_max=4, seed=1)
+    with pytest.raises(gpu.AtError) as e:                # block width 10 in y
+        st.run_ws(torch.zeros(st.shape, dtype=torch.float64, device="cuda"), 2)
+    assert e.value.status == gpu.AT_ERR_SHAPE
+    st = gpu.Stepper(dim=3, n=(64, 16, 16), p=(1, 2, 2), order=2, L=2, nu=0.02, dt=1e-4,
+                     nsteps_max=4, seed=1)
+    u = torch.zeros(st.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(gpu.AtError) as e:
+        st.run_ws(u, 2, scratch=u)
+    assert e.value.status == gpu.AT_ERR_ARG
