@@ -517,11 +517,11 @@ def bench_c1(args, torch, at, I):
 
 
 def bench_ws(args, torch, at, I):
-    """Weakly-synchronous runs with emergent delays (one workgroup per tile, no
-    global barrier, per-edge counters): N = 2^20, 1024 tiles of 1024 points,
-    order 2, 2000 steps, L = 3 against L = 0 (every step waits for both
-    neighbours: the synchronous algorithm), and the prescribed-delay path on
-    the same grid (autotuned steps per launch, delays U{0..3})."""
+    """Weakly-synchronous runs with emergent delays (one workgroup per tile or
+    block, no global barrier, level counters): 1D N = 2^20, 1024 tiles of 1024
+    points, order 2, 2000 steps, and 3D 512^3 with 8^3 blocks, 200 steps;
+    L = 3 against L = 0 (every step waits for its neighbours: the
+    synchronous algorithm), and the prescribed-delay path on the same grids."""
     import numpy as np
     wl = I.wl_adjoint_1d()
     N, P, nst = wl.n[0], wl.p[0], 2000
@@ -568,6 +568,47 @@ def bench_ws(args, torch, at, I):
     eprint("[ws] prescribed delays, fused s=%d: %.2f ms/run" % (fuse, ms))
     out["prescribed_L3"] = {"ms_per_run": round(ms, 3), "fuse_steps": fuse,
                             "updates_per_s": N * nst / (ms * 1e-3)}
+    # 3D: 512^3 x 3, 8^3 blocks of 64^3, one resident workgroup per block
+    w3 = I.wl_solenoidal_3d()
+    nst3 = w3.nsteps
+    v0 = torch.from_numpy(w3.u0).cuda()
+    v, s3 = torch.empty_like(v0), torch.empty_like(v0)
+    npt3 = w3.npoints
+    for L in (3, 0):
+        best, hist = None, None
+        for rep in range(max(1, min(args.steps, 2)) + 1):
+            st = at.Stepper(dim=3, n=w3.n, p=w3.p, order=2, L=L, nu=w3.nu, dt=w3.dt,
+                            nsteps_max=nst3, seed=w3.seed)
+            v.copy_(v0)
+            tm = Timer(torch)
+            tm.start()
+            st.run_ws(v, nst3, scratch=s3)
+            tm.stop()
+            ms = tm.total_ms()
+            if rep > 0 and (best is None or ms < best):
+                best = ms
+                hist = np.bincount(st.delays()[:nst3].ravel().astype(np.int64), minlength=L + 1)
+            del st
+        frac = (hist / hist.sum()).round(4).tolist()
+        eprint("[ws] 3D L=%d: %.1f ms/run (%.3f ms/step), delays k=0..%d: %s" %
+               (L, best, best / nst3, L, frac))
+        out["ws3d_L%d" % L] = {"ms_per_run": round(best, 3), "ms_per_step": round(best / nst3, 4),
+                              "point_updates_per_s": npt3 * nst3 / (best * 1e-3),
+                              "delay_fractions": frac}
+    st = at.Stepper(dim=3, n=w3.n, p=w3.p, order=2, L=3, nu=w3.nu, dt=w3.dt, nsteps_max=nst3,
+                    seed=w3.seed)
+    var = st.autotune(v0, 6)
+    snap = st.snapshot(v0)
+    st.restore(snap, v)
+    st.run(v, s3, nst3)
+    tm = Timer(torch)
+    st.restore(snap, v)
+    tm.start()
+    st.run(v, s3, nst3)
+    tm.stop()
+    ms = tm.total_ms()
+    eprint("[ws] 3D prescribed delays, variant %d: %.1f ms/run" % (var, ms))
+    out["prescribed3d_L3"] = {"ms_per_run": round(ms, 3), "kernel_variant": var}
     out["value"] = out["ws_L3_jitter0"]["updates_per_s"]
     out["unit"] = "grid-point updates/s (weakly-synchronous, emergent delays)"
     return out
