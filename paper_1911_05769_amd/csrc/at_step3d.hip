@@ -524,7 +524,7 @@ __device__ __forceinline__ void march3d(const Step3D &A, const double *const U0,
             const double lap = (D2x + D2y) + D2z;
             const double adv = (ux * D1x + uy * D1y) + uz * D1z;
             ov[c] = u + dt * (A.kappa[c] * lap - adv);
-            out[c * npt] = ov[c];
+            __builtin_nontemporal_store(ov[c], &out[c * npt]);
         }
         // publish the level-(n+1) values of points on block faces
         if (A.publish && (lx == 0 || lx == Wx - 1 || ly == 0 || ly == Wy - 1 || lz == 0 ||
