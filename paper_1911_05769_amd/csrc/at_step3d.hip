@@ -275,23 +275,6 @@ struct NbC {
     int k;
 };
 
-// Device-coherent load and store of a double (they read past, and write
-// through, the per-XCD L2): how the weakly-synchronous run moves ring values
-// between workgroups that may sit on different XCDs.
-__device__ __forceinline__ double ld_coherent(const double *p)
-{
-    return __longlong_as_double((long long)__hip_atomic_load(
-        reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED,
-        __HIP_MEMORY_SCOPE_AGENT));
-}
-
-__device__ __forceinline__ void st_coherent(double *p, double v)
-{
-    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
-                       (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-
 template <int NC, bool COH = false>
 __device__ __forceinline__ NbC<NC> load_nbc(const double *ring, const double *field, bool face,
                                             int k, bool stale, int64_t oring0, int64_t oring1,

@@ -30,6 +30,23 @@ __device__ __forceinline__ void ws_idle(int32_t jitter, uint64_t seed, int64_t w
     for (uint32_t i = 0; i < idle; ++i) __builtin_amdgcn_s_sleep(2);
 }
 
+// Device-coherent load and store of a double: they read past, and write
+// through, the per-XCD L2, so ring values pass between workgroups on
+// different XCDs without any cache-wide write-back or invalidate.
+__device__ __forceinline__ double ld_coherent(const double *p)
+{
+    return __longlong_as_double((long long)__hip_atomic_load(
+        reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED,
+        __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__device__ __forceinline__ void st_coherent(double *p, double v)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
+                       (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ int32_t load_relaxed(const int32_t *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

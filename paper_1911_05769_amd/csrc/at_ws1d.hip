@@ -33,23 +33,6 @@ namespace {
 
 constexpr int kWsThreads = 256;
 
-// Ring values move with device-scope (coherent) stores and loads: they write
-// through, and read past, the per-XCD L2, so no cache-wide write-back or
-// invalidate is needed to pass them between workgroups on different XCDs.
-__device__ __forceinline__ void ring_put(double *p, double v)
-{
-    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p),
-                       (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ double ring_get(const double *p)
-{
-    return __longlong_as_double((long long)__hip_atomic_load(
-        reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED,
-        __HIP_MEMORY_SCOPE_AGENT));
-}
-
 template <int ORDER, bool LINEAR, int PPT>
 __global__ __launch_bounds__(kWsThreads) void k_ws1d(Ws1D A)
 {
@@ -77,13 +60,13 @@ __global__ __launch_bounds__(kWsThreads) void k_ws1d(Ws1D A)
         if (t == 0) {
             double *e = edge(n, b, 0);
 #pragma unroll
-            for (int i = 0; i < H; ++i) ring_put(e + i, v[i]);
+            for (int i = 0; i < H; ++i) st_coherent(e + i, v[i]);
             announce(A.cnt + 2 * b + 0, (int32_t)n);
         }
         if (t == kWsThreads - 1) {
             double *e = edge(n, b, 1);
 #pragma unroll
-            for (int i = 0; i < H; ++i) ring_put(e + i, v[PPT - H + i]);
+            for (int i = 0; i < H; ++i) st_coherent(e + i, v[PPT - H + i]);
             announce(A.cnt + 2 * b + 1, (int32_t)n);
         }
     };
@@ -93,14 +76,14 @@ __global__ __launch_bounds__(kWsThreads) void k_ws1d(Ws1D A)
         const double *e0 = edge(n - k, q, s);
         if (k == 0 || stale) {
 #pragma unroll
-            for (int i = 0; i < H; ++i) out[i] = ring_get(e0 + i);
+            for (int i = 0; i < H; ++i) out[i] = ld_coherent(e0 + i);
             return;
         }
         const double *e1 = edge(n - k - 1, q, s);
         const double *e2 = M == 3 ? edge(n - k - 2, q, s) : e1;
 #pragma unroll
         for (int i = 0; i < H; ++i)
-            out[i] = extrap<false>(k, false, ring_get(e0 + i), ring_get(e1 + i), ring_get(e2 + i), M);
+            out[i] = extrap<false>(k, false, ld_coherent(e0 + i), ld_coherent(e1 + i), ld_coherent(e2 + i), M);
     };
 
     __syncthreads();                                  // s_stop initialised before any wait
