@@ -169,8 +169,9 @@ at_status at_run(at_ctx *ctx, double *u, double *scratch, int64_t nsteps);
  *              0..J units of about 128 clocks (hash of seed, tile, step),
  *              emulating uneven arrival
  *   spin_limit polls of a counter before a wait gives up (<= 0: 2^20)
- * Requirements: 1D: tile width W = 256 * q with q in {1, 2, 4, 8, 16} (q >= 2
- * for order 4); 3D: block widths multiples of 64 (x) and 8 (y).  All tiles or
+ * Requirements: 1D: tile width W = 256 q or 64 q with q in {1, 2, 4, 8, 16}
+ * (q >= 2 for order 4; one workgroup of 256 threads, or of one wave, per
+ * tile); 3D: block widths multiples of 64 (x) and 8 (y).  All tiles or
  * blocks must be resident at once (else AT_ERR_SHAPE: the launch is
  * cooperative; at_ws_capacity gives the limit).  Synchronous: returns after
  * the run.  AT_ERR_TIMEOUT if a wait gave up: every workgroup then leaves

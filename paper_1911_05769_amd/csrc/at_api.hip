@@ -619,12 +619,7 @@ at_status at_ws_capacity(const at_ctx *c, int64_t *max_tiles)
         *max_tiles = at3_ws_capacity(&c->cfg);
         return AT_OK;
     }
-    const int nt = ws1d_threads();
-    if (c->d.W % nt != 0) return AT_OK;
-    const int64_t ppt = c->d.W / nt;
-    if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8 && ppt != 16) return AT_OK;
-    if (ppt < c->d.h) return AT_OK;
-    *max_tiles = ws1d_max_tiles(c->d.order, c->cfg.adv_mode == 1, (int)ppt);
+    *max_tiles = ws1d_max_tiles(c->d.order, c->cfg.adv_mode == 1, c->d.W);
     return AT_OK;
 }
 
@@ -670,14 +665,12 @@ at_status at_run_ws(at_ctx *c, double *u, double *scratch, int64_t nsteps, int32
         c->n = nsteps;
         return AT_OK;
     }
-    const int nt = ws1d_threads();
-    if (d.W % nt != 0) return fail(AT_ERR_SHAPE, "tile width must be a multiple of %d", nt);
-    const int64_t ppt = d.W / nt;
-    if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8 && ppt != 16)
-        return fail(AT_ERR_SHAPE, "tile width must be %d x 1, 2, 4, 8 or 16", nt);
-    if (ppt < d.h) return fail(AT_ERR_SHAPE, "order 4 needs tile width >= %d", 2 * nt);
+    int nt = 0, ppt = 0;
+    if (!ws1d_shape(d.W, d.h, &nt, &ppt))
+        return fail(AT_ERR_SHAPE, "tile width must be 256 q or 64 q with q in {1, 2, 4, 8, 16} "
+                                  "(q >= 2 for order 4)");
     const bool linear = c->cfg.adv_mode == 1;
-    const int64_t maxt = ws1d_max_tiles(d.order, linear, (int)ppt);
+    const int64_t maxt = ws1d_max_tiles(d.order, linear, d.W);
     if (d.P > maxt)
         return fail(AT_ERR_SHAPE, "%lld tiles, but at most %lld workgroups can be resident at once",
                     (long long)d.P, (long long)maxt);
@@ -705,7 +698,7 @@ at_status at_run_ws(at_ctx *c, double *u, double *scratch, int64_t nsteps, int32
     a.coef.c1 = d.c1[0];
     a.coef.c2 = d.c2[0];
     a.coef.cadv = c->cfg.adv_speed;
-    AT_HIP(launch_ws1d(a, d.order, linear, (int)ppt, c->st));
+    AT_HIP(launch_ws1d(a, d.order, linear, c->st));
     int32_t herr = 0;
     AT_HIP(hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, c->st));
     AT_HIP(hipStreamSynchronize(c->st));

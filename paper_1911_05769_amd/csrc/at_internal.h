@@ -130,10 +130,10 @@ int adj1d_points_per_block();
 hipError_t launch_adj1d_fused(const AdjF &a, int order, bool linear, int ppt, int64_t nblocks,
                               size_t lds, hipStream_t st);
 size_t adj1d_fused_lds_bytes(int order, int S, int NT, int L);
-int ws1d_threads();
-int64_t ws1d_max_tiles(int order, bool linear, int ppt);
+bool ws1d_shape(int64_t W, int h, int *nt, int *ppt);
+int64_t ws1d_max_tiles(int order, bool linear, int64_t W);
 hipError_t launch_ws_init(int32_t *cnt, int64_t n, int32_t v, int32_t *err, hipStream_t st);
-hipError_t launch_ws1d(const Ws1D &a, int order, bool linear, int ppt, hipStream_t st);
+hipError_t launch_ws1d(const Ws1D &a, int order, bool linear, hipStream_t st);
 hipError_t launch_gnu_final(const double *part, int64_t nparts, double *out, hipStream_t st);
 hipError_t launch_stats(const double *u, int64_t n, double *part, double *out3, hipStream_t st);
 hipError_t launch_loss(const double *u, const double *t, double *lam, int64_t n, double *part,

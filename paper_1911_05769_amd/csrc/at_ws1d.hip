@@ -15,11 +15,12 @@
 // n-k-1(, n-k-2) of the neighbour's edge.  The delay actually used is stored
 // as k[n][f], so a run can be replayed exactly with prescribed delays.
 //
-// Work decomposition: one workgroup of 256 threads per tile (tile width
-// W = 256 * PPT), PPT consecutive points per thread held in registers for
-// the whole run; h values per side are traded with the neighbouring threads
-// through LDS each step.  Thread 0 receives the left halo and publishes the
-// tile's left edge, thread 255 the right ones.  All tiles must be resident at
+// Work decomposition: one workgroup of NT threads (256, or one wave of 64
+// for narrow tiles) per tile of width W = NT * PPT, PPT consecutive points
+// per thread held in registers for the whole run; h values per side are
+// traded with the neighbouring threads through LDS each step.  Thread 0
+// receives the left halo and publishes the tile's left edge, thread NT-1 the
+// right ones.  All tiles must be resident at
 // once (cooperative launch), and every wait is bounded: past the spin limit a
 // workgroup sets the error flag and leaves, and a waiting workgroup that sees
 // the flag leaves too, so every wave reaches the end of the kernel.
@@ -31,15 +32,13 @@ namespace atk {
 
 namespace {
 
-constexpr int kWsThreads = 256;
-
-template <int ORDER, bool LINEAR, int PPT>
-__global__ __launch_bounds__(kWsThreads) void k_ws1d(Ws1D A)
+template <int ORDER, bool LINEAR, int PPT, int NT>
+__global__ __launch_bounds__(NT) void k_ws1d(Ws1D A)
 {
     constexpr int H = ORDER / 2;
     constexpr int M = ORDER == 2 ? 2 : 3;
     static_assert(PPT >= H, "a thread holds at least h points");
-    __shared__ double lo[2][kWsThreads][H], hi[2][kWsThreads][H];
+    __shared__ double lo[2][NT][H], hi[2][NT][H];
     __shared__ int s_stop;
     const int t = threadIdx.x;
     const int64_t P = A.P, b = blockIdx.x;
@@ -63,7 +62,7 @@ __global__ __launch_bounds__(kWsThreads) void k_ws1d(Ws1D A)
             for (int i = 0; i < H; ++i) st_coherent(e + i, v[i]);
             announce(A.cnt + 2 * b + 0, (int32_t)n);
         }
-        if (t == kWsThreads - 1) {
+        if (t == NT - 1) {
             double *e = edge(n, b, 1);
 #pragma unroll
             for (int i = 0; i < H; ++i) st_coherent(e + i, v[PPT - H + i]);
@@ -101,7 +100,7 @@ __global__ __launch_bounds__(kWsThreads) void k_ws1d(Ws1D A)
         // only while the delay would pass its bound
         const int32_t kmax = (int32_t)min((int64_t)A.L, max((int64_t)0, n - M + 1));
         double hl[H], hr[H];
-        if (t == 0 || t == kWsThreads - 1) {
+        if (t == 0 || t == NT - 1) {
             const int s = t == 0 ? 1 : 0;                 // the neighbour's facing edge
             const int64_t q = t == 0 ? bl : br;
             const int32_t got = ws_wait(A.cnt + 2 * q + s, (int32_t)(n - kmax), A.err,
@@ -122,7 +121,7 @@ __global__ __launch_bounds__(kWsThreads) void k_ws1d(Ws1D A)
 #pragma unroll
         for (int i = 0; i < H; ++i) {
             ext[i] = t == 0 ? hl[i] : hi[buf][t - 1][i];
-            ext[H + PPT + i] = t == kWsThreads - 1 ? hr[i] : lo[buf][t + 1][i];
+            ext[H + PPT + i] = t == NT - 1 ? hr[i] : lo[buf][t + 1][i];
         }
 #pragma unroll
         for (int j = 0; j < PPT; ++j) ext[H + j] = v[j];
@@ -153,31 +152,50 @@ __global__ __launch_bounds__(256) void k_ws_init(int32_t *cnt, int64_t n, int32_
     if (i == 0) *err = 0;
 }
 
-// the kernel for (order, advection mode, points per thread), or null
-const void *ws1d_kernel(int order, bool linear, int ppt)
+}  // namespace
+
+// Threads per workgroup and points per thread for tile width W: 256 threads
+// when W = 256 q, else one wave when W = 64 q, with q in {1, 2, 4, 8, 16} and
+// q >= h; false when W fits neither.
+bool ws1d_shape(int64_t W, int h, int *nt, int *ppt)
 {
-#define WS_PICK(O, PP)                                                                         \
-    if (order == O && ppt == PP)                                                               \
-        return linear ? (const void *)k_ws1d<O, true, PP> : (const void *)k_ws1d<O, false, PP>;
-    WS_PICK(2, 1) WS_PICK(2, 2) WS_PICK(2, 4) WS_PICK(2, 8) WS_PICK(2, 16)
-    WS_PICK(4, 2) WS_PICK(4, 4) WS_PICK(4, 8) WS_PICK(4, 16)
+    for (const int t : {256, 64}) {
+        if (W % t != 0) continue;
+        const int64_t q = W / t;
+        if ((q == 1 || q == 2 || q == 4 || q == 8 || q == 16) && q >= h) {
+            *nt = t;
+            *ppt = (int)q;
+            return true;
+        }
+    }
+    return false;
+}
+
+// the kernel for (order, advection mode, points per thread, threads), or null
+static const void *ws1d_kernel(int order, bool linear, int ppt, int nt)
+{
+#define WS_PICK(O, PP, T)                                                                      \
+    if (order == O && ppt == PP && nt == T)                                                    \
+        return linear ? (const void *)k_ws1d<O, true, PP, T> : (const void *)k_ws1d<O, false, PP, T>;
+#define WS_PICK_T(T) WS_PICK(2, 1, T) WS_PICK(2, 2, T) WS_PICK(2, 4, T) WS_PICK(2, 8, T)          \
+    WS_PICK(2, 16, T) WS_PICK(4, 2, T) WS_PICK(4, 4, T) WS_PICK(4, 8, T) WS_PICK(4, 16, T)
+    WS_PICK_T(256)
+    WS_PICK_T(64)
+#undef WS_PICK_T
 #undef WS_PICK
     return nullptr;
 }
 
-}  // namespace
-
-int ws1d_threads() { return kWsThreads; }
-
 // Largest number of k_ws1d workgroups that can be resident at once for this
-// order and points per thread (0 if the variant does not exist)
-int64_t ws1d_max_tiles(int order, bool linear, int ppt)
+// order, advection mode and tile width (0 if the shape is not supported)
+int64_t ws1d_max_tiles(int order, bool linear, int64_t W)
 {
-    const void *f = ws1d_kernel(order, linear, ppt);
+    int nt = 0, ppt = 0;
+    if (!ws1d_shape(W, order / 2, &nt, &ppt)) return 0;
+    const void *f = ws1d_kernel(order, linear, ppt, nt);
     if (!f) return 0;
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kWsThreads, 0) != hipSuccess)
-        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, nt, 0) != hipSuccess) return 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
@@ -192,12 +210,14 @@ hipError_t launch_ws_init(int32_t *cnt, int64_t n, int32_t v, int32_t *err, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_ws1d(const Ws1D &a, int order, bool linear, int ppt, hipStream_t st)
+hipError_t launch_ws1d(const Ws1D &a, int order, bool linear, hipStream_t st)
 {
-    const void *f = ws1d_kernel(order, linear, ppt);
+    int nt = 0, ppt = 0;
+    if (!ws1d_shape(a.W, order / 2, &nt, &ppt)) return hipErrorInvalidValue;
+    const void *f = ws1d_kernel(order, linear, ppt, nt);
     if (!f) return hipErrorInvalidValue;
     void *args[] = {(void *)&a};
-    return hipLaunchCooperativeKernel(f, dim3((unsigned)a.P), dim3(kWsThreads), args, 0, st);
+    return hipLaunchCooperativeKernel(f, dim3((unsigned)a.P), dim3(nt), args, 0, st);
 }
 
 }  // namespace atk

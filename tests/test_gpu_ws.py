@@ -60,6 +60,11 @@ CASES = [
     ("o2_P2_q1_L15", 2 * 256, 2, 2, 15, False, False, 200, 300),
     ("o4_P3_q2_L1_one_step", 3 * 512, 3, 4, 1, False, False, 10, 1),
     ("o2_P7_q8_L4", 7 * 2048, 7, 2, 4, False, False, 50, 250),
+    # one-wave workgroups (W = 64 q)
+    ("o2_N1024_P8_W128_L2", 1024, 8, 2, 2, False, False, 30, 1000),
+    ("o4_P12_W128_L3", 12 * 128, 12, 4, 3, False, False, 40, 300),
+    ("o2_linear_P20_W64", 20 * 64, 20, 2, 2, True, False, 20, 300),
+    ("o4_stale_P6_W256_wave", 6 * 256, 6, 4, 3, False, True, 30, 200),
 ]
 
 
@@ -130,9 +135,9 @@ def test_ws_rejects(gpu):
             return e.status
         return gpu.AT_OK
 
-    assert status(n=4096, p=32) == gpu.AT_ERR_SHAPE          # W = 128
-    assert status(n=4096 * 3, p=16) == gpu.AT_ERR_SHAPE      # W = 768 (3 x 256)
-    assert status(order=4, n=4096, p=16) == gpu.AT_ERR_SHAPE  # W = 256 < 2 x 256
+    assert status(n=96 * 32, p=32) == gpu.AT_ERR_SHAPE       # W = 96
+    assert status(n=4096 * 3, p=16) == gpu.AT_ERR_SHAPE      # W = 768 (3 x 256, 12 x 64)
+    assert status(order=4, n=1024, p=16) == gpu.AT_ERR_SHAPE  # W = 64: one point per thread < h
     assert status(n=1 << 22, p=1 << 14) == gpu.AT_ERR_SHAPE  # more tiles than resident workgroups
     assert status(arith=1) == gpu.AT_ERR_ARG
     assert status(record=True, ckpt_every=5) == gpu.AT_ERR_STATE
@@ -163,11 +168,10 @@ def test_ws_bounded_wait_gives_up(gpu):
     assert relerr(host(u2), ref) <= TOL
 
 
-@pytest.mark.parametrize("order,q", [(2, 1), (4, 2), (2, 16)])
-def test_ws_at_resident_capacity(gpu, order, q):
+@pytest.mark.parametrize("order,W", [(2, 256), (4, 512), (2, 4096), (2, 64), (4, 128)])
+def test_ws_at_resident_capacity(gpu, order, W):
     """The most tiles the device can keep resident (reported by the library):
     the run succeeds there and replays exactly; one tile more is refused."""
-    W = 256 * q
     probe = gpu.Stepper(dim=1, n=W * 8, p=8, order=order, L=2, nu=0.02, dt=1e-5,
                         nsteps_max=1, seed=1)
     P = probe.ws_capacity()
