@@ -55,6 +55,35 @@ __device__ __forceinline__ int64_t ring_slot(const Step1D &a, int64_t d)
     return x;
 }
 
+// Level n0 of a region of E points that starts at periodic index G0w (in
+// [0, N)) into the padded LDS stage (point r at r + r/PPT), 0 past E.  Every
+// thread issues all of its PPT loads before its first LDS write, so their
+// latencies overlap.  Indices are wrapped into [0, N) (one subtraction when
+// the grid is at least one region wide), so every load is in bounds; the
+// values past E are loaded and dropped.
+template <int PPT>
+__device__ __forceinline__ void stage_region(const double *__restrict__ uin, int64_t N,
+                                             int64_t G0w, int E, int tid, double *stage)
+{
+    double v[PPT];
+    if (N >= (int64_t)kThreads * PPT) {
+#pragma unroll
+        for (int it = 0; it < PPT; ++it) {
+            int64_t g = G0w + it * kThreads + tid;
+            if (g >= N) g -= N;
+            v[it] = uin[g];
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < PPT; ++it) v[it] = uin[(G0w + it * kThreads + tid) % N];
+    }
+#pragma unroll
+    for (int it = 0; it < PPT; ++it) {
+        const int r = it * kThreads + tid;
+        stage[r + r / PPT] = r < E ? v[it] : 0.0;
+    }
+}
+
 template <int ORDER, bool LINEAR, bool FMA>
 __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
 {
@@ -76,17 +105,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
     if (G0w < 0) G0w += a.N;
 
     // ---- level n0 of the region: coalesced loads -> LDS -> registers
-#pragma unroll
-    for (int it = 0; it < PPT; ++it) {
-        const int r = it * kThreads + tid;
-        double v = 0.0;
-        if (r < E) {
-            int64_t g = G0w + r;
-            while (g >= a.N) g -= a.N;
-            v = a.uin[g];
-        }
-        stage[r + r / PPT] = v;
-    }
+    stage_region<PPT>(a.uin, a.N, G0w, E, tid, stage);
     __syncthreads();
     double w[PPT + 2 * H];
 #pragma unroll
@@ -252,17 +271,46 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     int64_t G0w = G0 % a.N;
     if (G0w < 0) G0w += a.N;
 
-#pragma unroll
-    for (int it = 0; it < PPT; ++it) {
-        const int r = it * kThreads + tid;
-        double v = 0.0;
-        if (r < E) {
-            int64_t g = G0w + r;
-            while (g >= a.N) g -= a.N;
-            v = a.uin[g];
+    // ---- sources of the LDS copies of this launch's delays and of the ring
+    // levels below n0 (eh row d holds level n0 - D + d; kd[(t*NT + tl)*2 +
+    // side] the delay of region tile tl's face at level n0 + t).  A thread's
+    // first element of each is loaded together with the field, so that its
+    // latency overlaps theirs.
+    const int D = a.D;
+    int8_t *kd = reinterpret_cast<int8_t *>(eh + (size_t)(D + S - 1) * a.NT * 2 * H);
+    int64_t tb = floordiv(G0, a.W) % a.P;
+    if (tb < 0) tb += a.P;
+    const int nk = FUSED ? S * a.NT * 2 : 0;
+    const int nr = FUSED ? D * a.NT * 2 * H : 0;
+    auto kd_src = [&](int e) -> int64_t {
+        const int side = e & 1;
+        const int tl = (e >> 1) % a.NT;
+        const int t = (e >> 1) / a.NT;
+        const int64_t tp = (tb + tl) % a.P;
+        return (a.n0 + t) * (2 * a.P) + 2 * tp + side;
+    };
+    auto eh_src = [&](int e) -> int64_t {                 // -1: a level before the start
+        const int q = e % H;
+        const int side = (e / H) & 1;
+        const int tl = (e / (2 * H)) % a.NT;
+        const int d = (e / (2 * H)) / a.NT;
+        const int64_t lev = a.n0 - D + d;
+        if (lev < 0) return -1;
+        const int64_t tp = (tb + tl) % a.P;
+        return ((ring_slot(a, lev - a.n0) * a.P + tp) * 2 + side) * H + q;
+    };
+    int8_t k_first = 0;
+    double e_first = 0.0;
+    int64_t e_first_at = -1;
+    if constexpr (FUSED) {
+        if (tid < nk) k_first = a.delays[kd_src(tid)];
+        if (tid < nr) {
+            e_first_at = eh_src(tid);
+            if (e_first_at >= 0) e_first = a.ring[e_first_at];
         }
-        stage[r + r / PPT] = v;
     }
+
+    stage_region<PPT>(a.uin, a.N, G0w, E, tid, stage);
     __syncthreads();
     double w[PPT + 2 * H];
 #pragma unroll
@@ -271,34 +319,13 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     for (int q = 0; q < H; ++q) { w[q] = 0.0; w[PPT + H + q] = 0.0; }
     __syncthreads();
 
-    // ---- LDS copies of this launch's delays and of the ring levels below n0
-    // (eh row d holds level n0 - D + d; kd[(t*NT + tl)*2 + side] the delay
-    // of region tile tl's face at level n0 + t)
-    const int D = a.D;
-    int8_t *kd = reinterpret_cast<int8_t *>(eh + (size_t)(D + S - 1) * a.NT * 2 * H);
     if constexpr (FUSED) {
-        int64_t tb = floordiv(G0, a.W) % a.P;
-        if (tb < 0) tb += a.P;
-        const int64_t F2 = 2 * a.P;
-        const int nk = S * a.NT * 2;
-        for (int e = tid; e < nk; e += kThreads) {
-            const int side = e & 1;
-            const int tl = (e >> 1) % a.NT;
-            const int t = (e >> 1) / a.NT;
-            const int64_t tp = (tb + tl) % a.P;
-            kd[e] = a.delays[(a.n0 + t) * F2 + 2 * tp + side];
-        }
-        const int nr = D * a.NT * 2 * H;
-        for (int e = tid; e < nr; e += kThreads) {
-            const int q = e % H;
-            const int side = (e / H) & 1;
-            const int tl = (e / (2 * H)) % a.NT;
-            const int d = (e / (2 * H)) / a.NT;
-            const int64_t lev = a.n0 - D + d;
-            if (lev >= 0) {
-                const int64_t tp = (tb + tl) % a.P;
-                eh[e] = a.ring[((ring_slot(a, lev - a.n0) * a.P + tp) * 2 + side) * H + q];
-            }
+        if (tid < nk) kd[tid] = k_first;
+        for (int e = tid + kThreads; e < nk; e += kThreads) kd[e] = a.delays[kd_src(e)];
+        if (e_first_at >= 0) eh[tid] = e_first;
+        for (int e = tid + kThreads; e < nr; e += kThreads) {
+            const int64_t at = eh_src(e);
+            if (at >= 0) eh[e] = a.ring[at];
         }
     }
 
