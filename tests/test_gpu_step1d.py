@@ -210,6 +210,32 @@ def test_snapshot_restore_bitwise(gpu):
     assert np.array_equal(host(u), full)
 
 
+@pytest.mark.parametrize("N,P,off", [(1001, 7, 0), (1001, 7, 1), (4096, 8, 1), (4096, 8, 0)])
+def test_state_copy_paths_bitwise(gpu, N, P, off):
+    """Snapshot and restore copy the field 16 bytes per thread when both
+    pointers are 16-byte aligned (an odd last value on its own) and 8 bytes
+    per thread otherwise; the field given as a view at an 8-byte offset takes
+    the second path.  Every path restores the state bit for bit."""
+    u0, dt = _inputs(N, 0.02)
+    log("  copy case N=%d P=%d offset=%d" % (N, P, off))
+    st = stepper(gpu, N, P, 2, 2, 0.02, dt, 40)
+    base = torch.zeros(N + 1, dtype=torch.float64, device="cuda")
+    u = base[off:off + N]
+    u.copy_(dev(u0))
+    s = torch.empty(N, dtype=torch.float64, device="cuda")
+    st.run(u, s, 20)
+    ref = u.clone()
+    snap = st.snapshot(u)
+    st.run(u, s, 20)
+    u.fill_(0.0)
+    st.restore(snap, u)
+    assert st.n == 20
+    assert torch.equal(u, ref)
+    st.run(u, s, 20)
+    full, _ = gpu_run(gpu, u0, N, P, 2, 2, 0.02, dt, 40)
+    assert np.array_equal(host(u), full)
+
+
 def test_autotune_keeps_bits(gpu):
     N, P, nst = 20000, 40, 120
     u0, dt = _inputs(N, 0.01)
