@@ -228,9 +228,10 @@ def host_info():
 
 
 def copy_ceiling(torch, n=1 << 27, reps=5):
-    """Achieved rate of a plain device copy of n doubles (read + write), on
-    the same stream and with the same events as the kernels: the practical
-    HBM ceiling next to the 8 TB/s nameplate."""
+    """Achieved rate of torch's device copy of n doubles (read + write; the
+    runtime's device-to-device copy), on the same stream and with the same
+    events as the kernels.  The library's own copy kernel streams faster
+    (copy_ceiling_lib)."""
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     dst.copy_(src)
