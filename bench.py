@@ -33,7 +33,7 @@ METRIC = "grid-point updates/s & % HBM peak (AT step, adjoint, batched) vs plain
 # reported while the kernel source is the one the counters were taken on.
 TRAFFIC = {"sources": ["paper_1911_05769_amd/csrc/at_step1d.hip",
                        "paper_1911_05769_amd/csrc/at_stencil1d.h"],
-           "md5": "d9e481710f548358c892d3c379bc0c30", "fuse": 56,
+           "md5": "481dd4cd90ecb5e6b4722b97d6b59a25", "fuse": 56,
            "bytes_per_launch": (73225.3 * 2.0 + 145294.2) * 1024}
 
 
