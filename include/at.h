@@ -199,8 +199,9 @@ at_status at_autotune(at_ctx *ctx, const double *u0, double *t1, double *t2,
  * per-point halos (tile rows, prefetch depth, register budget), 6..8 and
  * 12..14 LDS-tiled with halos in the tile rims and 1 to 4 planes prefetched
  * (block widths multiples of the tile, AT_ERR_ARG otherwise), 9..11
- * barrier-free column march.  1D contexts accept
- * only 0. */
+ * barrier-free column march.  1D contexts: 0 automatic; 1, 2, 3 for 16, 8
+ * and 4 points per thread in the fused launches (the tile width must be
+ * divisible by it, AT_ERR_ARG otherwise); every choice gives the same bits. */
 at_status at_set_variant(at_ctx *ctx, int32_t variant);
 
 /* Current step n, steps per launch in use, ring levels R. */
