@@ -166,11 +166,12 @@ def max_threads() -> int:
 
 
 def stats(u) -> tuple:
-    """(max|u|, mean u, sum|u|) with serial Neumaier sums."""
+    """(max|u|, mean u, sum|u|, count of non-finite values) with serial
+    Neumaier sums; max|u| is NaN when any value is NaN."""
     u = np.ascontiguousarray(u, dtype=np.float64).ravel()
-    out = np.empty(3, dtype=np.float64)
+    out = np.empty(4, dtype=np.float64)
     lib().or_stats(u.size, _ptr(u), _ptr(out))
-    return float(out[0]), float(out[1]), float(out[2])
+    return float(out[0]), float(out[1]), float(out[2]), int(out[3])
 
 
 def loss(u, target):

@@ -506,19 +506,26 @@ int or_run3d(const int64_t *nxyz, const int64_t *pxyz, int L, int halo_mode,
 /* Reductions (serial order, Neumaier-compensated sums)                      */
 /* ------------------------------------------------------------------------ */
 
-/* out[0] = max|u|, out[1] = mean(u), out[2] = sum |u| */
+/* out[0] = max|u|, out[1] = mean(u), out[2] = sum |u|, out[3] = the number of
+ * values that are not finite.  The maximum is NaN as soon as one value is
+ * NaN (a NaN compares false with everything, so a plain running maximum would
+ * skip it and report a finite maximum for a field that has blown up). */
 void or_stats(int64_t n, const double *u, double *out)
 {
     double mx = 0.0, s = 0.0, c = 0.0, a = 0.0, ac = 0.0;
+    int64_t bad = 0;
     for (int64_t i = 0; i < n; ++i) {
         double v = fabs(u[i]);
-        if (v > mx) mx = v;
+        if (isnan(v)) mx = v;
+        else if (v > mx) mx = v;
+        if (!isfinite(u[i])) ++bad;
         neumaier_add(&s, &c, u[i]);
         neumaier_add(&a, &ac, v);
     }
     out[0] = mx;
     out[1] = (s + c) / (double)n;
     out[2] = a + ac;
+    out[3] = (double)bad;
 }
 
 /* J = 0.5 * sum (u - target)^2 ; lam = u - target (= dJ/du) */

@@ -470,8 +470,8 @@ def test_stats_and_loss_against_exact_sums():
     g = np.random.default_rng(5)
     u = g.standard_normal(100003) * 10.0 ** g.uniform(-8, 8, 100003)
     t = g.standard_normal(100003)
-    mx, mean, sabs = oracle.stats(u)
-    assert mx == np.max(np.abs(u))
+    mx, mean, sabs, bad = oracle.stats(u)
+    assert mx == np.max(np.abs(u)) and bad == 0
     assert abs(mean - math.fsum(u.tolist()) / u.size) <= 1e-15 * sabs / u.size
     assert abs(sabs - math.fsum(np.abs(u).tolist())) <= 2e-16 * sabs
     J, lam = oracle.loss(u, t)
@@ -479,6 +479,23 @@ def test_stats_and_loss_against_exact_sums():
     assert np.array_equal(lam, d)
     ref = math.fsum((0.5 * (d * d)).tolist())
     assert abs(J - ref) <= 2e-16 * ref
+
+
+def test_stats_flag_non_finite_values():
+    """A field that has blown up must not report a finite maximum: NumPy's
+    max propagates NaN, and the count is that of the non-finite entries."""
+    g = np.random.default_rng(6)
+    u = g.standard_normal(4099)
+    for bad_idx, vals in (([7], [np.nan]), ([0, 4098], [np.inf, -np.inf]),
+                          ([5, 600, 601], [np.nan, np.inf, 1.0])):
+        x = u.copy()
+        x[bad_idx] = vals
+        mx, mean, sabs, bad = oracle.stats(x)
+        ref = np.max(np.abs(x))
+        assert (np.isnan(mx) and np.isnan(ref)) or mx == ref
+        assert bad == int(np.sum(~np.isfinite(x)))
+    mx, _, _, bad = oracle.stats(np.full(10, np.nan))
+    assert np.isnan(mx) and bad == 10
 
 
 # --------------------------------------------------------------------------
