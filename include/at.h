@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define AT_ABI_VERSION 3
+#define AT_ABI_VERSION 4
 #define AT_MAX_SCALARS 4      /* passive scalars a 3D context may carry         */
 
 typedef enum {
@@ -186,6 +186,28 @@ at_status at_run_ws(at_ctx *ctx, double *u, double *scratch, int64_t nsteps, int
  * when its tile or block shape is not one at_run_ws supports. */
 at_status at_ws_capacity(const at_ctx *ctx, int64_t *max_tiles);
 
+/* Graph replay of at_run: 1 captures the launch sequence of an at_run call
+ * into a HIP graph (on a private stream the library creates; no launch runs
+ * during the capture) and replays it on the context's stream; the graph is
+ * kept and replayed again while a later call has the same start step, step
+ * count, fields, steps per launch, kernel variant and debug flags (for
+ * example a run restarted from the same snapshot), and captured anew
+ * otherwise.  0 (default): launches are issued one by one.  Results are
+ * bit-identical either way.  The graph removes the per-launch host cost of
+ * the one-launch-per-step form on small grids. */
+at_status at_set_graph(at_ctx *ctx, int32_t use_graph);
+
+/* Debug aids.  AT_DEBUG_POISON_RING: after every launch, every ring slot that
+ * no later step may read is overwritten with NaN (1D: levels below n - L -
+ * m + 1 once level n is reached; 3D: below n - L - 1), and the ring starts
+ * filled with NaN instead of zeros, so a step reading a level outside the
+ * window that the delay bound L allows (section 2) would carry a NaN into
+ * the field.  Results are unchanged when the indexing is right.  Costs one
+ * pass over the ring per launch.  Not available in record mode
+ * (AT_ERR_STATE): the adjoint re-reads every level. */
+#define AT_DEBUG_POISON_RING 1
+at_status at_set_debug(at_ctx *ctx, int32_t flags);
+
 /* Choose steps-per-launch s (1D) or the kernel variant (3D) -- nothing that
  * changes results -- by timing `trial_steps` steps from u0 for each
  * candidate; requires n == 0 and leaves the context at n = 0 with the ring
@@ -212,15 +234,23 @@ at_status at_query(const at_ctx *ctx, int64_t *n, int32_t *fuse_steps, int32_t *
 at_status at_delays_copy(const at_ctx *ctx, int8_t *host_out);
 
 /* Snapshot / restore of the full stepper state (the field u at the current
- * step, the ring and n).  at_snapshot_bytes gives the device buffer size. */
+ * step, the ring and n).  at_snapshot_bytes gives the device buffer size.
+ * Both are asynchronous on the context's stream.  at_restore of a buffer that
+ * this context filled by at_snapshot (recognised by its address) takes the
+ * step from the context; any other buffer is read once on the host to find
+ * its step, which waits for the stream, and AT_ERR_ARG if it holds none. */
 at_status at_snapshot_bytes(const at_ctx *ctx, uint64_t *bytes);
 at_status at_snapshot(at_ctx *ctx, const double *u, void *dev_buf);
 at_status at_restore(at_ctx *ctx, const void *dev_buf, double *u);
 
-/* Reductions over a field of the context's size, written to device memory:
- * out3[0] = max |u|, out3[1] = mean u, out3[2] = sum |u| (wave64 shuffles,
- * compensated per-workgroup partials, fixed-order final pass). */
-at_status at_stats(at_ctx *ctx, const double *u, double *out3);
+/* Reductions over a field of the context's size, written to device memory
+ * (wave64 shuffles, compensated per-workgroup partials, fixed-order final
+ * pass): out4[0] = max |u|, NaN as soon as one value is NaN; out4[1] = mean u;
+ * out4[2] = sum |u|; out4[3] = the number of values that are not finite
+ * (NaN or +-inf), as a double.  A run that has become unstable (the AT
+ * extrapolation with large delays can amplify, section 2) shows up as
+ * out4[3] > 0 instead of a finite maximum. */
+at_status at_stats(at_ctx *ctx, const double *u, double *out4);
 
 /* Final-time misfit J = 0.5 * sum (u - target)^2 into *J_dev, and
  * lambda = u - target (= dJ/du) into lam (may be NULL). */

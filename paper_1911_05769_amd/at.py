@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import math
 import os
+import sys
 from typing import Optional, Sequence
 
 import numpy as np
@@ -18,12 +19,13 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libat.so")
 
-AT_ABI_VERSION = 3
+AT_ABI_VERSION = 4
 AT_MAX_SCALARS = 4
 AT_OK, AT_ERR_ARG, AT_ERR_SHAPE, AT_ERR_DELAY, AT_ERR_HIP, AT_ERR_NOMEM, AT_ERR_STATE, \
     AT_ERR_TIMEOUT = 0, -1, -2, -3, -4, -5, -6, -7
 DELAY_GENERATE, DELAY_HOST = 0, 1
 DIST_UNIFORM, DIST_HALF_ZERO = 0, 1
+DEBUG_POISON_RING = 1
 STATUS_NAMES = {0: "AT_OK", -1: "AT_ERR_ARG", -2: "AT_ERR_SHAPE", -3: "AT_ERR_DELAY",
                 -4: "AT_ERR_HIP", -5: "AT_ERR_NOMEM", -6: "AT_ERR_STATE",
                 -7: "AT_ERR_TIMEOUT"}
@@ -87,6 +89,8 @@ SIGNATURES = {
     "at_set_fuse": (ctypes.c_int, [_P, ctypes.c_int32]),
     "at_set_adjoint_fuse": (ctypes.c_int, [_P, ctypes.c_int32]),
     "at_set_variant": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "at_set_graph": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "at_set_debug": (ctypes.c_int, [_P, ctypes.c_int32]),
     "at_query": (ctypes.c_int, [_P, _P, _P, _P]),
     "at_delays_copy": (ctypes.c_int, [_P, _P]),
     "at_snapshot_bytes": (ctypes.c_int, [_P, _P]),
@@ -243,11 +247,20 @@ class Stepper:
         _check(lib().at_init(ctypes.byref(self.cfg), ctypes.byref(self._ctx)), "at_init")
         self.cfg.delays_host = None
 
+    def close(self):
+        """Release the library handle (host memory only; the workspace tensor
+        is freed with this object).  Idempotent."""
+        if getattr(self, "_ctx", None):
+            lib().at_free(self._ctx)
+            self._ctx = ctypes.c_void_p(None)
+
     def __del__(self):
+        # never call into the library while the interpreter shuts down: the
+        # HIP runtime may already be tearing itself down by then
+        if sys.is_finalizing():
+            return
         try:
-            if self._ctx:
-                lib().at_free(self._ctx)
-                self._ctx = ctypes.c_void_p(None)
+            self.close()
         except Exception:
             pass
 
@@ -302,6 +315,14 @@ class Stepper:
     def set_variant(self, v: int):
         _check(lib().at_set_variant(self._ctx, int(v)), "at_set_variant")
 
+    def set_graph(self, on: bool = True):
+        """Replay run() from a captured HIP graph (see at_set_graph)."""
+        _check(lib().at_set_graph(self._ctx, 1 if on else 0), "at_set_graph")
+
+    def set_debug(self, flags: int):
+        """AT_DEBUG_* flags, e.g. DEBUG_POISON_RING (see at_set_debug)."""
+        _check(lib().at_set_debug(self._ctx, int(flags)), "at_set_debug")
+
     def query(self):
         n, s, R = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().at_query(self._ctx, ctypes.byref(n), ctypes.byref(s), ctypes.byref(R)),
@@ -331,7 +352,9 @@ class Stepper:
 
     # -- reductions, loss, adjoint -----------------------------------------
     def stats(self, u: torch.Tensor) -> torch.Tensor:
-        out = torch.empty(3, dtype=torch.float64, device=self.device)
+        """(max|u|, mean u, sum|u|, count of non-finite values) on the device;
+        max|u| is NaN when any value is NaN."""
+        out = torch.empty(4, dtype=torch.float64, device=self.device)
         _check(lib().at_stats(self._ctx, self._f(u, "u"), _ptr(out)), "at_stats")
         return out
 
@@ -389,11 +412,18 @@ class Batch:
                for w in wls]
         return cls(ins, device=device, fuse_steps=fuse_steps)
 
+    def close(self):
+        """Release the batch handle, its cached graph and capture stream.
+        Idempotent."""
+        if getattr(self, "_h", None):
+            lib().at_batch_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
-            if self._h:
-                lib().at_batch_free(self._h)
-                self._h = ctypes.c_void_p(None)
+            self.close()
         except Exception:
             pass
 

@@ -7,7 +7,11 @@ adjoint (libat.so's at_run in record mode and at_adjoint).
 
 Gradients are those of the discrete map with dt held fixed: the same delay
 array is replayed, and the forward keeps a checkpoint every ``ckpt_every``
-steps from which the reverse sweep recomputes each segment.
+steps from which the reverse sweep recomputes each segment.  The forward
+advances ``fuse_steps`` steps per launch (the library lowers it to what the
+grid allows); the adjoint's reverse launches are fused as far as the grid
+allows.  All work runs on the stream that is current when the function is
+applied.
 """
 from __future__ import annotations
 
@@ -32,6 +36,7 @@ class StepSpec:
     dist: int = at.DIST_UNIFORM
     length: float = 2 * math.pi
     halo_mode: int = 0
+    fuse_steps: int = 64       # steps per forward launch (clamped to the grid's limit)
 
 
 class AtBurgers(torch.autograd.Function):
@@ -40,18 +45,20 @@ class AtBurgers(torch.autograd.Function):
         st = at.Stepper(n=spec.n, p=spec.p, order=spec.order, L=spec.L, nu=float(nu),
                         dt=spec.dt, nsteps_max=spec.nsteps, length=spec.length,
                         halo_mode=spec.halo_mode, seed=spec.seed, dist=spec.dist, record=True,
-                        ckpt_every=spec.ckpt_every, device=u0.device)
+                        ckpt_every=spec.ckpt_every, fuse_steps=spec.fuse_steps,
+                        device=u0.device)
         u = u0.detach().contiguous().clone()
         scratch = torch.empty_like(u)
         st.run(u, scratch, spec.nsteps)
         ctx.stepper = st
-        ctx.nu_shape = nu.shape
+        ctx.nu_meta = (nu.shape, nu.device, nu.dtype)
         return u
 
     @staticmethod
     def backward(ctx, grad_uT: torch.Tensor):
         g, gnu = ctx.stepper.adjoint(grad_uT.contiguous())
-        return g, gnu.reshape(ctx.nu_shape), None
+        shape, device, dtype = ctx.nu_meta
+        return g, gnu.reshape(shape).to(device=device, dtype=dtype), None
 
 
 class AtMisfit(torch.autograd.Function):
@@ -76,8 +83,13 @@ _reducers = {}
 
 
 def _reducer(n: int, device) -> at.Stepper:
-    """A minimal context whose only use is the reduction kernels."""
-    key = (n, str(device))
+    """A minimal context whose only use is the reduction kernels, bound to the
+    stream that is current now (a context launches on the stream it was made
+    with, so one is kept per stream)."""
+    device = torch.device(device)
+    if device.index is None:
+        device = torch.device(device.type, torch.cuda.current_device())
+    key = (n, str(device), torch.cuda.current_stream(device).cuda_stream)
     if key not in _reducers:
         _reducers[key] = at.Stepper(n=n, p=1, order=2, L=0, nu=0.0, dt=1.0, nsteps_max=0,
                                     device=device)

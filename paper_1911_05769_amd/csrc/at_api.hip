@@ -196,6 +196,17 @@ struct at_ctx {
     int fuse;
     int variant;     // 3D kernel variant (tile rows, prefetch depth, register budget)
     int adj_fuse = 0;   // reverse steps per adjoint launch: 0 automatic, 1 one-step kernel
+    int debug = 0;      // AT_DEBUG_* flags (at_set_debug)
+    // graph replay of at_run (at_set_graph): the launch sequence of one call,
+    // captured on a private stream and replayed on the context's stream
+    int use_graph = 0;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int64_t g_n0 = -1, g_nsteps = -1;
+    const double *g_u = nullptr, *g_s = nullptr;
+    int g_fuse = 0, g_variant = -1, g_debug = -1;
+    // snapshots taken through this context: device buffer and its step
+    std::vector<std::pair<const void *, int64_t>> snaps;
 };
 
 namespace {
@@ -222,7 +233,7 @@ at_status make_layout(const at_config *c, const Derived &d, Layout &L)
     L.ring = off;
     off = align_up(off + 8ull * (uint64_t)L.R * ring_level_doubles(c, d));
     L.red = off;
-    off = align_up(off + 8ull * (kRedBlocks * 5 + 16));
+    off = align_up(off + 8ull * (kRedBlocks * 6 + 16));
     // level counters of the weakly-synchronous run (1D: [P][2] tile edges;
     // 3D: one per block), then its error flag
     L.sync = off;
@@ -373,6 +384,53 @@ int max_fuse(const at_ctx *c)
     return c->d.dim == 1 ? max_fuse_1d(c->d) : at3_max_fuse(c);
 }
 
+// Ring levels a later launch may still read once the context has reached
+// level n1: 1D, the L + m - 1 levels below n1 (a step n reads levels down to
+// n - L - m + 1 and publishes level n itself); 3D, levels n1 - L - 1 .. n1
+// (a step reads levels down to n - L - 1, and level n's faces are published
+// before it).  Levels below 0 are never read (start-up clamp).
+void live_levels(const at_ctx *c, int64_t n1, int64_t *lo, int64_t *hi)
+{
+    if (c->d.dim == 1) {
+        *lo = n1 - (c->cfg.L + c->d.m - 1);
+        *hi = n1 - 1;
+    } else {
+        *lo = n1 - c->cfg.L - 1;
+        *hi = n1;
+    }
+    if (*lo < 0) *lo = 0;
+}
+
+// Debug mode AT_DEBUG_POISON_RING: after every launch, every ring slot that
+// holds no live level is overwritten with NaN, so a step that read a level it
+// must not would carry the NaN into the field.
+hipError_t poison_ring(at_ctx *c, int64_t n1)
+{
+    if (!(c->debug & AT_DEBUG_POISON_RING)) return hipSuccess;
+    int64_t lo, hi;
+    live_levels(c, n1, &lo, &hi);
+    const int64_t R = c->lay.R;
+    const int64_t nlive = hi >= lo ? std::min<int64_t>(hi - lo + 1, R) : 0;
+    return launch_poison(c->ring, R, (int64_t)ring_level_doubles(&c->cfg, c->d),
+                         (int)(lo % R), (int)nlive, c->st);
+}
+
+// Clear the whole ring: zeros, or NaN in the poisoning debug mode (no level is
+// live before the first step)
+hipError_t clear_ring(at_ctx *c)
+{
+    const double v = (c->debug & AT_DEBUG_POISON_RING) ? __builtin_nan("") : 0.0;
+    return launch_fill(c->ring, (int64_t)c->lay.R * (int64_t)ring_level_doubles(&c->cfg, c->d),
+                       v, c->st);
+}
+
+void drop_graph(at_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->g_n0 = c->g_nsteps = -1;
+}
+
 // Region of a fused reverse launch of s steps (8 points per thread, aligned)
 struct RegionAdj {
     int64_t RL, CH;
@@ -505,7 +563,38 @@ at_status at_init(const at_config *cfg, at_ctx **out)
     return AT_OK;
 }
 
-void at_free(at_ctx *c) { delete c; }
+void at_free(at_ctx *c)
+{
+    if (!c) return;
+    drop_graph(c);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    delete c;
+}
+
+at_status at_set_graph(at_ctx *c, int32_t use_graph)
+{
+    if (!c) return fail(AT_ERR_ARG, "null context");
+    if (use_graph != 0 && use_graph != 1) return fail(AT_ERR_ARG, "use_graph must be 0 or 1");
+    c->use_graph = use_graph;
+    if (!use_graph) drop_graph(c);
+    return AT_OK;
+}
+
+at_status at_set_debug(at_ctx *c, int32_t flags)
+{
+    if (!c) return fail(AT_ERR_ARG, "null context");
+    if (flags & ~AT_DEBUG_POISON_RING) return fail(AT_ERR_ARG, "unknown debug flags 0x%x", flags);
+    if ((flags & AT_DEBUG_POISON_RING) && c->cfg.record)
+        return fail(AT_ERR_STATE, "ring poisoning is not available in record mode (the adjoint "
+                                  "re-reads every level)");
+    const bool was = c->debug & AT_DEBUG_POISON_RING;
+    c->debug = flags;
+    if ((flags & AT_DEBUG_POISON_RING) && !was) {
+        if (c->n == 0) AT_HIP(clear_ring(c));
+        else AT_HIP(poison_ring(c, c->n));
+    }
+    return AT_OK;
+}
 
 at_status at_set_fuse(at_ctx *c, int32_t s)
 {
@@ -576,17 +665,16 @@ at_status at_step(at_ctx *c, const double *u_in, double *u_out)
     at_status st = launch_any(c, u_in, u_out, c->n, 1, 1);
     if (st) return st;
     c->n += 1;
+    AT_HIP(poison_ring(c, c->n));
     return AT_OK;
 }
 
-at_status at_run(at_ctx *c, double *u, double *scratch, int64_t nsteps)
+namespace {
+
+// the launch sequence of at_run on c->st (recorded into a graph when c->st is
+// a capturing stream); advances c->n
+at_status run_launches(at_ctx *c, double *u, double *scratch, int64_t nsteps)
 {
-    if (!c || !u || !scratch) return fail(AT_ERR_ARG, "null argument");
-    if (u == scratch) return fail(AT_ERR_ARG, "u and scratch must differ");
-    if (nsteps < 0) return fail(AT_ERR_ARG, "nsteps < 0");
-    if (c->n + nsteps > c->cfg.nsteps_max)
-        return fail(AT_ERR_STATE, "run to step %lld beyond nsteps_max %lld",
-                    (long long)(c->n + nsteps), (long long)c->cfg.nsteps_max);
     double *cur = u, *oth = scratch;
     int64_t left = nsteps;
     const int64_t C = c->cfg.ckpt_every;
@@ -606,8 +694,64 @@ at_status at_run(at_ctx *c, double *u, double *scratch, int64_t nsteps)
         std::swap(cur, oth);
         c->n += s;
         left -= s;
+        AT_HIP(poison_ring(c, c->n));
     }
     if (cur != u) AT_HIP(launch_copy(u, cur, field_doubles(c), c->st));
+    return AT_OK;
+}
+
+}  // namespace
+
+at_status at_run(at_ctx *c, double *u, double *scratch, int64_t nsteps)
+{
+    if (!c || !u || !scratch) return fail(AT_ERR_ARG, "null argument");
+    if (u == scratch) return fail(AT_ERR_ARG, "u and scratch must differ");
+    if (nsteps < 0) return fail(AT_ERR_ARG, "nsteps < 0");
+    if (c->n + nsteps > c->cfg.nsteps_max)
+        return fail(AT_ERR_STATE, "run to step %lld beyond nsteps_max %lld",
+                    (long long)(c->n + nsteps), (long long)c->cfg.nsteps_max);
+    if (!c->use_graph || nsteps == 0) return run_launches(c, u, scratch, nsteps);
+    // graph replay: the cached graph applies when it was captured for the same
+    // start step, length, fields and launch choices
+    if (!(c->gexec && c->g_n0 == c->n && c->g_nsteps == nsteps && c->g_u == u &&
+          c->g_s == scratch && c->g_fuse == c->fuse && c->g_variant == c->variant &&
+          c->g_debug == c->debug)) {
+        drop_graph(c);
+        if (!c->cap) AT_HIP(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+        const int64_t n0 = c->n;
+        hipStream_t own = c->st;
+        c->st = c->cap;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+        at_status st = AT_OK;
+        if (e == hipSuccess) {
+            st = run_launches(c, u, scratch, nsteps);
+            hipError_t e2 = hipStreamEndCapture(c->cap, &g);
+            if (e2 != hipSuccess && st == AT_OK) e = e2;
+        }
+        c->st = own;
+        c->n = n0;
+        if (st) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return fail(AT_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            c->gexec = nullptr;
+            return fail(AT_ERR_HIP, "graph instantiate: %s", hipGetErrorString(e));
+        }
+        c->g_n0 = n0;
+        c->g_nsteps = nsteps;
+        c->g_u = u;
+        c->g_s = scratch;
+        c->g_fuse = c->fuse;
+        c->g_variant = c->variant;
+        c->g_debug = c->debug;
+    }
+    AT_HIP(hipGraphLaunch(c->gexec, c->st));
+    c->n += nsteps;
     return AT_OK;
 }
 
@@ -728,34 +872,43 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
     }
     hipEvent_t e0, e1;
     AT_HIP(hipEventCreate(&e0));
-    AT_HIP(hipEventCreate(&e1));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(AT_ERR_HIP, "at_autotune: hipEventCreate failed");
+    }
     float best_ms = 1e30f;
     int best = cands[0];
-    const uint64_t rlev = ring_level_doubles(&c->cfg, c->d);
-    for (int s : cands) {
+    const int keep_graph = c->use_graph;
+    c->use_graph = 0;                         // time the launches themselves
+    at_status st = AT_OK;
+    for (size_t i = 0; i < cands.size() && st == AT_OK; ++i) {
+        const int s = cands[i];
         float ms_best = 1e30f;
-        for (int rep = 0; rep < 2; ++rep) {
-            AT_HIP(launch_fill(c->ring, (int64_t)c->lay.R * (int64_t)rlev, 0.0, c->st));
-            AT_HIP(launch_copy(t1, u0, field_doubles(c), c->st));
+        for (int rep = 0; rep < 2 && st == AT_OK; ++rep) {
+            hipError_t e = clear_ring(c);
+            if (e == hipSuccess) e = launch_copy(t1, u0, field_doubles(c), c->st);
             c->n = 0;
             if (c->d.dim == 1) c->fuse = s;
             else c->variant = s;
-            AT_HIP(hipEventRecord(e0, c->st));
-            at_status st = at_run(c, t1, t2, trial_steps);
-            if (st) { c->n = 0; return st; }
-            AT_HIP(hipEventRecord(e1, c->st));
-            AT_HIP(hipEventSynchronize(e1));
+            if (e == hipSuccess) e = hipEventRecord(e0, c->st);
+            if (e == hipSuccess) st = at_run(c, t1, t2, trial_steps);
+            if (e == hipSuccess && st == AT_OK) e = hipEventRecord(e1, c->st);
+            if (e == hipSuccess && st == AT_OK) e = hipEventSynchronize(e1);
             float ms = 0.f;
-            AT_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (e == hipSuccess && st == AT_OK) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess && st == AT_OK)
+                st = fail(AT_ERR_HIP, "at_autotune: %s", hipGetErrorString(e));
             ms_best = std::min(ms_best, ms);
         }
-        if (ms_best < best_ms * 0.98f) { best_ms = ms_best; best = s; }
+        if (st == AT_OK && ms_best < best_ms * 0.98f) { best_ms = ms_best; best = s; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    AT_HIP(launch_fill(c->ring, (int64_t)c->lay.R * (int64_t)rlev, 0.0, c->st));
-    AT_HIP(hipStreamSynchronize(c->st));
+    c->use_graph = keep_graph;
     c->n = 0;
+    if (st) return st;
+    AT_HIP(clear_ring(c));
+    AT_HIP(hipStreamSynchronize(c->st));
     if (c->d.dim == 1) c->fuse = best;
     else c->variant = best;
     if (chosen) *chosen = best;
@@ -786,10 +939,13 @@ at_status at_snapshot(at_ctx *c, const double *u, void *dev_buf)
     char *b = (char *)dev_buf;
     AT_HIP(launch_copy((double *)b, u, nu, c->st));
     AT_HIP(launch_copy((double *)(b + align_up(8 * nu)), c->ring, nr, c->st));
-    double nn = (double)c->n;   // step counter, exact below 2^53
-    AT_HIP(hipMemcpyAsync(b + align_up(8 * nu) + align_up(8 * nr), &nn, sizeof nn,
-                          hipMemcpyHostToDevice, c->st));
-    AT_HIP(hipStreamSynchronize(c->st));
+    // the step counter, exact below 2^53, written by a kernel (no host buffer
+    // has to outlive the call, so nothing waits)
+    AT_HIP(launch_fill((double *)(b + align_up(8 * nu) + align_up(8 * nr)), 1, (double)c->n,
+                       c->st));
+    for (auto &e : c->snaps)
+        if (e.first == dev_buf) { e.second = c->n; return AT_OK; }
+    c->snaps.emplace_back(dev_buf, c->n);
     return AT_OK;
 }
 
@@ -798,23 +954,31 @@ at_status at_restore(at_ctx *c, const void *dev_buf, double *u)
     if (!c || !u || !dev_buf) return fail(AT_ERR_ARG, "null argument");
     const uint64_t nu = field_doubles(c), nr = (uint64_t)c->lay.R * ring_level_doubles(&c->cfg, c->d);
     const char *b = (const char *)dev_buf;
-    double nn = 0.0;
-    AT_HIP(hipMemcpyAsync(&nn, b + align_up(8 * nu) + align_up(8 * nr), sizeof nn,
-                          hipMemcpyDeviceToHost, c->st));
-    AT_HIP(hipStreamSynchronize(c->st));
-    if (!(nn >= 0.0) || nn > (double)c->cfg.nsteps_max || nn != floor(nn))
-        return fail(AT_ERR_ARG, "buffer does not hold a snapshot of this context");
+    // a buffer this context filled: its step is known on the host; any other
+    // buffer: read the step it holds (the only case that waits for the stream)
+    int64_t step = -1;
+    for (const auto &e : c->snaps)
+        if (e.first == dev_buf) step = e.second;
+    if (step < 0) {
+        double nn = 0.0;
+        AT_HIP(hipMemcpyAsync(&nn, b + align_up(8 * nu) + align_up(8 * nr), sizeof nn,
+                              hipMemcpyDeviceToHost, c->st));
+        AT_HIP(hipStreamSynchronize(c->st));
+        if (!(nn >= 0.0) || nn > (double)c->cfg.nsteps_max || nn != floor(nn))
+            return fail(AT_ERR_ARG, "buffer does not hold a snapshot of this context");
+        step = (int64_t)nn;
+    }
     AT_HIP(launch_copy(u, (const double *)b, nu, c->st));
     AT_HIP(launch_copy(c->ring, (const double *)(b + align_up(8 * nu)), nr, c->st));
-    c->n = (int64_t)nn;
+    c->n = step;
     return AT_OK;
 }
 
-at_status at_stats(at_ctx *c, const double *u, double *out3)
+at_status at_stats(at_ctx *c, const double *u, double *out4)
 {
-    if (!c || !u || !out3) return fail(AT_ERR_ARG, "null argument");
+    if (!c || !u || !out4) return fail(AT_ERR_ARG, "null argument");
     const int64_t n = field_doubles(c);
-    AT_HIP(launch_stats(u, n, c->red, out3, c->st));
+    AT_HIP(launch_stats(u, n, c->red, out4, c->st));
     return AT_OK;
 }
 

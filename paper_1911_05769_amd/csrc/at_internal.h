@@ -115,6 +115,7 @@ __device__ __forceinline__ Acc wave_acc(Acc a)
 hipError_t launch_delays(int8_t *out, int64_t nsteps, int64_t F, int L, int m, int dist,
                          uint64_t seed, hipStream_t st);
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
+hipError_t launch_poison(double *ring, int64_t R, int64_t lev, int s0, int nlive, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
 size_t step1d_lds_bytes(int order, int s, int NT, int D, int ppt);
 int step1d_points_per_thread();
@@ -135,7 +136,7 @@ int64_t ws1d_max_tiles(int order, bool linear, int64_t W);
 hipError_t launch_ws_init(int32_t *cnt, int64_t n, int32_t v, int32_t *err, hipStream_t st);
 hipError_t launch_ws1d(const Ws1D &a, int order, bool linear, hipStream_t st);
 hipError_t launch_gnu_final(const double *part, int64_t nparts, double *out, hipStream_t st);
-hipError_t launch_stats(const double *u, int64_t n, double *part, double *out3, hipStream_t st);
+hipError_t launch_stats(const double *u, int64_t n, double *part, double *out4, hipStream_t st);
 hipError_t launch_loss(const double *u, const double *t, double *lam, int64_t n, double *part,
                        double *J, hipStream_t st);
 

@@ -1,5 +1,5 @@
-// 1D kernels of libat.so for gfx950: delay generator, AT stepper (one or
-// several fused steps per launch), fills/copies and reductions.
+// 1D stepper kernels of libat.so for gfx950: the AT stepper with one or
+// several fused steps per launch, and its batched form.
 //
 // Method: viscous Burgers u_t + u u_x = nu u_xx (or linear advection c u_x),
 // central differences and forward Euler (paper section 3.2) on P tiles of a
@@ -478,171 +478,6 @@ __global__ __launch_bounds__(kThreads) void k_step1d_aligned_batch(const Step1D 
     step1d_aligned_body<ORDER, LINEAR, FMA>(a, e.y);
 }
 
-// Delay array: SplitMix64 (Steele, Lea & Flood 2014) output for the state
-// seed + gamma*(1 + n*F + f), mapped to the distribution by a multiply-shift
-// of the high 32 bits, then clamped to min(k, L, max(0, n - m + 1)).
-__global__ void k_delays(int8_t *out, int64_t total, int64_t F, int L, int m, int dist,
-                         uint64_t seed)
-{
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        uint64_t z = seed + 0x9E3779B97F4A7C15ULL * (uint64_t)(idx + 1);
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-        z = z ^ (z >> 31);
-        const uint64_t hi = z >> 32, lo = z & 0xFFFFFFFFULL;
-        int k;
-        if (dist == 0) k = (int)((hi * (uint64_t)(L + 1)) >> 32);
-        else k = (L == 0 || lo < 0x80000000ULL) ? 0 : 1 + (int)((hi * (uint64_t)L) >> 32);
-        const int64_t n = idx / F;
-        int64_t lim = n - m + 1;
-        if (lim < 0) lim = 0;
-        if (lim > L) lim = L;
-        out[idx] = (int8_t)(k < lim ? k : lim);
-    }
-}
-
-__global__ void k_fill(double *p, int64_t n, double v)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
-}
-
-__global__ void k_copy(double *__restrict__ dst, const double *__restrict__ src, int64_t n)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
-}
-
-// One 16-byte element per thread and no loop, so every workgroup moves one
-// contiguous 4 KiB block: the form that streams fastest here (about 6.2 TB/s
-// for 1 GiB, against about 5.1 for the runtime's device-to-device copy).  The
-// odd last double, if any, is copied by thread 0.
-__global__ __launch_bounds__(kThreads) void k_copy16(double2 *__restrict__ dst,
-                                                     const double2 *__restrict__ src, int64_t n2,
-                                                     double *dtail, const double *stail)
-{
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i < n2) dst[i] = src[i];
-    if (dtail && i == 0) *dtail = *stail;
-}
-
-// ---------------------------------------------------------------------------
-// Reductions: per-thread compensated accumulation, wave64 shuffles, one
-// partial per workgroup, then a single-workgroup pass in fixed order.
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ double wave_max(double v)
-{
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-    return v;
-}
-
-// part[b*5 + {0..4}] = max|u|, sum u (s, c), sum|u| (s, c)
-__global__ __launch_bounds__(kThreads) void k_stats_part(const double *u, int64_t n, double *part)
-{
-    double mx = 0.0;
-    Acc s{0.0, 0.0}, sa{0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kThreads) {
-        const double v = u[i];
-        mx = fmax(mx, fabs(v));
-        acc_add(s, v);
-        acc_add(sa, fabs(v));
-    }
-    mx = wave_max(mx);
-    s = wave_acc(s);
-    sa = wave_acc(sa);
-    __shared__ double red[kThreads / 64][5];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[wv][0] = mx; red[wv][1] = s.s; red[wv][2] = s.c; red[wv][3] = sa.s; red[wv][4] = sa.c;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = red[0][0];
-        Acc S{red[0][1], red[0][2]}, SA{red[0][3], red[0][4]};
-        for (int q = 1; q < kThreads / 64; ++q) {
-            m = fmax(m, red[q][0]);
-            acc_merge(S, Acc{red[q][1], red[q][2]});
-            acc_merge(SA, Acc{red[q][3], red[q][4]});
-        }
-        double *o = part + (int64_t)blockIdx.x * 5;
-        o[0] = m; o[1] = S.s; o[2] = S.c; o[3] = SA.s; o[4] = SA.c;
-    }
-}
-
-__global__ void k_stats_final(const double *part, int nb, int64_t n, double *out3)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double m = 0.0;
-    Acc S{0.0, 0.0}, SA{0.0, 0.0};
-    for (int b = 0; b < nb; ++b) {
-        const double *o = part + (int64_t)b * 5;
-        m = fmax(m, o[0]);
-        acc_merge(S, Acc{o[1], o[2]});
-        acc_merge(SA, Acc{o[3], o[4]});
-    }
-    out3[0] = m;
-    out3[1] = (S.s + S.c) / (double)n;
-    out3[2] = SA.s + SA.c;
-}
-
-// part[b*2 + {0,1}] = sum 0.5 d^2 (s, c); lam = d = u - t
-__global__ __launch_bounds__(kThreads) void k_loss_part(const double *u, const double *t,
-                                                       double *lam, int64_t n, double *part)
-{
-    Acc s{0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kThreads) {
-        const double d = u[i] - t[i];
-        if (lam) lam[i] = d;
-        acc_add(s, 0.5 * (d * d));
-    }
-    s = wave_acc(s);
-    __shared__ double red[kThreads / 64][2];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) { red[wv][0] = s.s; red[wv][1] = s.c; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        Acc S{red[0][0], red[0][1]};
-        for (int q = 1; q < kThreads / 64; ++q) acc_merge(S, Acc{red[q][0], red[q][1]});
-        part[(int64_t)blockIdx.x * 2] = S.s;
-        part[(int64_t)blockIdx.x * 2 + 1] = S.c;
-    }
-}
-
-// out = sum of the compensated pairs part[i*2], part[i*2+1] in a fixed
-// order: thread t merges pairs t, t+256, ... in turn, each wave combines its
-// lanes by the fixed shuffle tree, wave 0 the four wave sums in order
-__global__ __launch_bounds__(kThreads) void k_pairs_final(const double *part, int64_t np,
-                                                          double *out)
-{
-    __shared__ double red[kThreads / 64][2];
-    const int t = threadIdx.x;
-    Acc S{0.0, 0.0};
-#pragma unroll 4
-    for (int64_t b = t; b < np; b += kThreads) acc_merge(S, Acc{part[b * 2], part[b * 2 + 1]});
-    S = wave_acc(S);
-    if ((t & 63) == 0) { red[t >> 6][0] = S.s; red[t >> 6][1] = S.c; }
-    __syncthreads();
-    if (t == 0) {
-        Acc T{0.0, 0.0};
-        for (int w = 0; w < kThreads / 64; ++w) acc_merge(T, Acc{red[w][0], red[w][1]});
-        out[0] = T.s + T.c;
-    }
-}
-
-int grid_for(int64_t n)
-{
-    int64_t g = (n + kThreads - 1) / kThreads;
-    if (g > 4096) g = 4096;
-    if (g < 1) g = 1;
-    return (int)g;
-}
-
 }  // namespace
 
 int step1d_points_per_thread() { return kPPT; }
@@ -717,66 +552,6 @@ hipError_t launch_step1d_batch(const Step1D *descs, const int2 *tbl, int64_t nbl
         else { if (fma) AT_BATCH(4, false, true); else AT_BATCH(4, false, false); }
     }
 #undef AT_BATCH
-    return hipGetLastError();
-}
-
-hipError_t launch_delays(int8_t *out, int64_t nsteps, int64_t F, int L, int m, int dist,
-                         uint64_t seed, hipStream_t st)
-{
-    const int64_t total = nsteps * F;
-    if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_delays, dim3(grid_for(total)), dim3(kThreads), 0, st, out, total, F, L,
-                       m, dist, seed);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(kThreads), 0, st, p, n, v);
-    return hipGetLastError();
-}
-
-hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st)
-{
-    if (n <= 0) return hipSuccess;
-    const int64_t n2 = n / 2;
-    const int64_t blocks = (n2 + kThreads - 1) / kThreads;
-    const bool aligned = (((uintptr_t)dst | (uintptr_t)src) & 15) == 0;
-    if (aligned && n2 > 0 && blocks <= 0x7fffffff) {
-        double *dt = (n & 1) ? dst + (n - 1) : nullptr;
-        const double *stl = (n & 1) ? src + (n - 1) : nullptr;
-        hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(kThreads), 0, st,
-                           reinterpret_cast<double2 *>(dst), reinterpret_cast<const double2 *>(src),
-                           n2, dt, stl);
-    } else {
-        hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(kThreads), 0, st, dst, src, n);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_stats(const double *u, int64_t n, double *part, double *out3, hipStream_t st)
-{
-    int nb = grid_for(n);
-    if (nb > kRedBlocks) nb = kRedBlocks;
-    hipLaunchKernelGGL(k_stats_part, dim3(nb), dim3(kThreads), 0, st, u, n, part);
-    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(64), 0, st, part, nb, n, out3);
-    return hipGetLastError();
-}
-
-hipError_t launch_loss(const double *u, const double *t, double *lam, int64_t n, double *part,
-                       double *J, hipStream_t st)
-{
-    int nb = grid_for(n);
-    if (nb > kRedBlocks) nb = kRedBlocks;
-    hipLaunchKernelGGL(k_loss_part, dim3(nb), dim3(kThreads), 0, st, u, t, lam, n, part);
-    hipLaunchKernelGGL(k_pairs_final, dim3(1), dim3(kThreads), 0, st, part, (int64_t)nb, J);
-    return hipGetLastError();
-}
-
-hipError_t launch_gnu_final(const double *part, int64_t nparts, double *out, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_pairs_final, dim3(1), dim3(kThreads), 0, st, part, nparts, out);
     return hipGetLastError();
 }
 

@@ -24,9 +24,32 @@ def test_more_than_one_gpu_exits_with_message():
     assert r.stdout == ""
 
 
-def test_counter_bytes_match_the_committed_kernel_source():
+def test_counter_bytes_only_for_the_measured_kernel_source():
     """roofline.traffic is reported only while the hashed sources are the ones
-    the counters were taken on; the stored hash must be the current one."""
+    the counters were taken on, for the same steps per launch and the exact
+    arithmetic; otherwise it is null."""
     b = _bench_module()
-    assert b.sources_md5(b.TRAFFIC["sources"]) == b.TRAFFIC["md5"]
-    assert b.TRAFFIC["bytes_per_launch"] > 0
+    cur = b.sources_md5(b.TRAFFIC["sources"])
+    r = {"s": b.TRAFFIC["fuse"], "arith": 0}
+    saved = dict(b.TRAFFIC)
+    try:
+        b.TRAFFIC.update(md5=cur, bytes_per_launch=123456.0)
+        assert b.measured_traffic(r) == 123456
+        assert b.measured_traffic(dict(r, s=r["s"] + 1)) is None
+        assert b.measured_traffic(dict(r, arith=1)) is None
+        b.TRAFFIC.update(md5="0" * 32)
+        assert b.measured_traffic(r) is None
+    finally:
+        b.TRAFFIC.clear()
+        b.TRAFFIC.update(saved)
+    if saved["md5"] is not None:        # stored counters belong to the current source
+        assert saved["md5"] == cur and saved["bytes_per_launch"] > 0
+
+
+def test_roofline_uses_published_peaks():
+    b = _bench_module()
+    r = {"s": 56, "arith": 0, "gbps": 530.0, "tflops": 29.4, "issue_ceiling": 44.5}
+    dom, other = b.roofline(r)
+    assert dom["bound"] == "alu" and dom["peak"] == 78.6
+    assert abs(dom["frac"] - 29.4 / 78.6) < 1e-4
+    assert other["bound"] == "hbm" and other["peak"] == 8000.0

@@ -258,8 +258,8 @@ def test_stats_and_loss(gpu):
         if st is None:
             continue
         out = host(st.stats(dev(x)))
-        mx, mean, sabs = oracle.stats(x)
-        assert out[0] == mx
+        mx, mean, sabs, bad = oracle.stats(x)
+        assert out[0] == mx and out[3] == bad == 0
         assert abs(out[1] - mean) <= 1e-15 * sabs / n
         assert abs(out[2] - sabs) <= 1e-15 * sabs
         lam = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -267,6 +267,23 @@ def test_stats_and_loss(gpu):
         Jr, lr = oracle.loss(x, y)
         assert abs(J - Jr) <= 1e-14 * Jr
         assert np.array_equal(host(lam), lr)
+
+
+def test_stats_flag_non_finite(gpu):
+    """A NaN or an infinity anywhere (first or last point, inside a partial's
+    stride) makes max|u| NaN (or inf) and is counted, as in the oracle."""
+    n = (1 << 20) + 37
+    x = np.random.default_rng(4).standard_normal(n)
+    st = gpu.Stepper(n=n, p=1, order=2, L=0, nu=0.0, dt=1.0, nsteps_max=1)
+    for idx, vals in (([0], [np.nan]), ([n - 1], [np.inf]), ([12345, 700001], [-np.inf, np.nan]),
+                      ([5, 6, 7], [np.inf, np.inf, np.inf])):
+        y = x.copy()
+        y[idx] = vals
+        out = host(st.stats(dev(y)))
+        mx, _, _, bad = oracle.stats(y)
+        assert out[3] == bad == len(idx)
+        assert (np.isnan(out[0]) and np.isnan(mx)) or out[0] == mx == np.inf
+        log("  non-finite at %s: max %r, count %d" % (idx, out[0], int(out[3])))
 
 
 def test_mean_conserved_sync_on_gpu(gpu):

@@ -102,13 +102,21 @@ def test_every_kernel_variant_same_bits(gpu, n, p):
         assert np.array_equal(o, outs[0]), "variant %d differs" % v
 
 
+def _faces_reach_L(k, L):
+    """True when, in the steps compared, delay L occurs on x-, y- and z-faces
+    (face f = 6 b + 2 axis + side)."""
+    F = k.shape[1]
+    return all(bool((k[:, a * 2 + s::6] == L).any()) for a in range(3) for s in range(2)
+               if a * 2 + s < F)
+
+
 def test_full_size_3d_first_steps(gpu):
-    """512^3 x 3 components, 8^3 blocks of 64^3, L = 3: the first 4 steps on the
-    whole grid against the oracle (the start-up clamp allows delays from
-    step 1 on)."""
+    """512^3 x 3 components, 8^3 blocks of 64^3, L = 3: the first 8 steps on the
+    whole grid against the oracle.  The start-up clamp allows delays up to
+    min(L, n - 1), so steps 4..7 use k = L = 3 on faces of every axis."""
     wl = I.wl_solenoidal_3d()
-    nst = 4
-    log("3d full size", wl.name)
+    nst = 8
+    log("3d full size", wl.name, nst, "steps")
     outs = {}
     for var in (0, 7, 14):          # 7: the variant the benchmark's autotuner picks
         st = gpu.Stepper(dim=3, n=wl.n, p=wl.p, order=2, L=wl.L, nu=wl.nu, dt=wl.dt,
@@ -120,6 +128,7 @@ def test_full_size_3d_first_steps(gpu):
         k = st.delays()
         outs[var] = host(u)
         del s, u
+    assert _faces_reach_L(k[:nst], wl.L)
     ref = oracle.run3d(wl.u0, wl.n, wl.p, wl.L, wl.nu, wl.dt, k, nst)
     for var, got in outs.items():
         err = relerr(got, ref)
