@@ -252,6 +252,20 @@ at_status at_restore(at_ctx *ctx, const void *dev_buf, double *u);
  * out4[3] > 0 instead of a finite maximum. */
 at_status at_stats(at_ctx *ctx, const double *u, double *out4);
 
+/* at_stats without a context, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops): the same
+ * kernels and the same four outputs as at_stats, for n doubles at u
+ * (1 <= n <= AT_NOALLOC_MAX_POINTS, AT_ERR_ARG otherwise), launched on
+ * `stream` (a hipStream_t; NULL for the null stream) of the current device.
+ * The per-workgroup partials live in a static device array of 1024 x 6
+ * doubles (48 KiB) that each GPU the library runs on keeps until the process
+ * ends; its address is looked up once per device on the first call there.
+ * Nothing is allocated or freed.  Every call on one GPU shares that array,
+ * so calls that can overlap on one GPU (other streams, other threads) race
+ * and must be ordered by the caller.  Asynchronous; out4 is device memory. */
+#define AT_NOALLOC_MAX_POINTS ((int64_t)1 << 40)
+at_status at_stats_noalloc(const double *u, int64_t n, double *out4, void *stream);
+
 /* Final-time misfit J = 0.5 * sum (u - target)^2 into *J_dev, and
  * lambda = u - target (= dJ/du) into lam (may be NULL). */
 at_status at_loss(at_ctx *ctx, const double *u, const double *target, double *lam,

@@ -97,6 +97,7 @@ SIGNATURES = {
     "at_snapshot": (ctypes.c_int, [_P, _P, _P]),
     "at_restore": (ctypes.c_int, [_P, _P, _P]),
     "at_stats": (ctypes.c_int, [_P, _P, _P]),
+    "at_stats_noalloc": (ctypes.c_int, [_P, ctypes.c_int64, _P, _P]),
     "at_loss": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "at_adjoint": (ctypes.c_int, [_P, _P, _P, _P]),
     "at_batch_workspace_bytes": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
@@ -148,6 +149,18 @@ def _require_f64_cuda(t: torch.Tensor, numel: int, what: str):
         raise TypeError("%s must be a CUDA float64 tensor" % what)
     if not t.is_contiguous() or t.numel() != numel:
         raise ValueError("%s must be contiguous with %d elements" % (what, numel))
+
+
+def stats_noalloc(u: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    """at_stats_noalloc on the current stream: (max|u|, mean u, sum|u|, count
+    of non-finite values) of the CUDA float64 tensor u into the 4-element
+    CUDA float64 tensor out, with no allocation by the library."""
+    _require_f64_cuda(u, u.numel(), "u")
+    _require_f64_cuda(out, 4, "out")
+    stream = torch.cuda.current_stream(u.device).cuda_stream
+    _check(lib().at_stats_noalloc(_ptr(u), u.numel(), _ptr(out), ctypes.c_void_p(stream)),
+           "at_stats_noalloc")
+    return out
 
 
 def levels_for_order(order: int) -> int:

@@ -1,7 +1,12 @@
 // Utility kernels of libat.so for gfx950: the delay generator, fills, the
 // ring-poisoning debug pass, device copies and the reductions (diagnostics,
 // misfit, dJ/dnu).  None of them is part of a time step.
+#include <mutex>
+
+#include "../../include/at.h"
 #include "at_internal.h"
+
+at_status at_fail(at_status st, const char *msg);   // at_api.hip: keeps the message
 
 namespace atk {
 
@@ -274,3 +279,70 @@ hipError_t launch_gnu_final(const double *part, int64_t nparts, double *out, hip
 }
 
 }  // namespace atk
+
+// ---------------------------------------------------------------------------
+// at_stats_noalloc: the diagnostics reduction with its per-workgroup partials
+// in a static device array instead of a context's workspace
+// ---------------------------------------------------------------------------
+
+namespace atk {
+
+namespace {
+
+// partials of the first reduction pass: kRedBlocks workgroups x 6 doubles
+// (48 KiB); each GPU the library runs on holds its own copy until the
+// process ends.  In host code this name is only a stand-in for the symbol:
+// kernels get the device address that hipGetSymbolAddress returns.
+__device__ __align__(256) double scratch[kRedBlocks * 6];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device, looked up once per
+// device (with that device current)
+hipError_t scratch_on_current_device(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+}  // namespace atk
+
+extern "C" {
+
+at_status at_stats_noalloc(const double *u, int64_t n, double *out4, void *stream)
+{
+    using namespace atk;
+    char msg[160];
+    if (!u || !out4) return at_fail(AT_ERR_ARG, "at_stats_noalloc: null argument");
+    if (n < 1 || n > AT_NOALLOC_MAX_POINTS) {
+        snprintf(msg, sizeof msg, "at_stats_noalloc: n = %lld outside 1..%lld", (long long)n,
+                 (long long)AT_NOALLOC_MAX_POINTS);
+        return at_fail(AT_ERR_ARG, msg);
+    }
+    double *part = nullptr;
+    hipError_t e = scratch_on_current_device(&part);
+    if (e == hipSuccess) e = launch_stats(u, n, part, out4, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        snprintf(msg, sizeof msg, "at_stats_noalloc: %s", hipGetErrorString(e));
+        return at_fail(AT_ERR_HIP, msg);
+    }
+    return AT_OK;
+}
+
+}  // extern "C"
+
