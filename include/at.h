@@ -208,7 +208,8 @@ at_status at_set_graph(at_ctx *ctx, int32_t use_graph);
 #define AT_DEBUG_POISON_RING 1
 at_status at_set_debug(at_ctx *ctx, int32_t flags);
 
-/* Choose steps-per-launch s (1D) or the kernel variant (3D) -- nothing that
+/* Choose steps-per-launch s (1D) or the kernel variant (3D, including the
+ * two-step variants) -- nothing that
  * changes results -- by timing `trial_steps` steps from u0 for each
  * candidate; requires n == 0 and leaves the context at n = 0 with the ring
  * cleared.  u0 is not modified; t1 and t2 are two scratch fields.
@@ -221,7 +222,14 @@ at_status at_autotune(at_ctx *ctx, const double *u0, double *t1, double *t2,
  * per-point halos (tile rows, prefetch depth, register budget), 6..8 and
  * 12..14 LDS-tiled with halos in the tile rims and 1 to 4 planes prefetched
  * (block widths multiples of the tile, AT_ERR_ARG otherwise), 9..11
- * barrier-free column march.  1D contexts: 0 automatic; 1, 2, 3 for 16, 8
+ * barrier-free column march, 15 and 16 two steps per launch (levels n ->
+ * n+2 in one z-march of 64 x 8 or 64 x 4 tiles: each workgroup recomputes
+ * level n+1 on a one-point rim around its tile as the neighbouring block
+ * would, and takes it from the ring's AT levels where the step-(n+1) delay
+ * is positive; block widths multiples of 64 in x and of the tile rows in y).
+ * Choosing 15 or 16 sets the steps per launch to 2 (a run's odd last step
+ * and at_step use a one-step variant); choosing another sets it to 1, and
+ * at_set_fuse(ctx, 2) selects 15 (or 16).  1D contexts: 0 automatic; 1, 2, 3 for 16, 8
  * and 4 points per thread in the fused launches (the tile width must be
  * divisible by it, AT_ERR_ARG otherwise); every choice gives the same bits. */
 at_status at_set_variant(at_ctx *ctx, int32_t variant);

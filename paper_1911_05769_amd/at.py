@@ -267,13 +267,13 @@ class Stepper:
             lib().at_free(self._ctx)
             self._ctx = ctypes.c_void_p(None)
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # never call into the library while the interpreter shuts down: the
-        # HIP runtime may already be tearing itself down by then
-        if sys.is_finalizing():
-            return
+        # HIP runtime may already be tearing itself down by then (the check is
+        # bound at definition time: module globals may be gone at exit)
         try:
-            self.close()
+            if not _finalizing():
+                self.close()
         except Exception:
             pass
 
@@ -432,11 +432,10 @@ class Batch:
             lib().at_batch_free(self._h)
             self._h = ctypes.c_void_p(None)
 
-    def __del__(self):
-        if sys.is_finalizing():
-            return
+    def __del__(self, _finalizing=sys.is_finalizing):
         try:
-            self.close()
+            if not _finalizing():
+                self.close()
         except Exception:
             pass
 

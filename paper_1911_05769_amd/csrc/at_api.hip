@@ -345,6 +345,8 @@ at_status at3_publish(at_ctx *c, const double *u, int64_t n);
 int at3_max_fuse(const at_ctx *c);
 int at3_variants();
 bool at3_variant_ok(const at_config *c, int var);
+bool at3_is_fused(int var);
+int at3_single_variant(const at_config *c, int var);
 int64_t at3_ws_capacity(const at_config *c);
 at_status at3_launch_ws(at_ctx *ctx, double *u, double *scratch, int64_t n0, int64_t nsteps,
                         int32_t *cnt, int32_t *err, int8_t *delays, int32_t jitter, uint64_t seed,
@@ -545,6 +547,8 @@ at_status at_init(const at_config *cfg, at_ctx **out)
     if (d.dim == 3)   // the first variant with a build for this component count
         while (!at3_variant_ok(&c->cfg, c->variant)) ++c->variant;
     c->fuse = cfg->fuse_steps > 0 ? std::min(cfg->fuse_steps, max_fuse(c)) : 1;
+    if (d.dim == 3 && c->fuse == 2)   // two steps per launch: the two-step kernel
+        c->variant = at3_variant_ok(&c->cfg, 15) ? 15 : 16;
     hipError_t e = hipSuccess;
     if (cfg->delay_mode == AT_DELAY_GENERATE)
         e = launch_delays(c->delays, cfg->nsteps_max, d.F, cfg->L, d.m, cfg->delay_dist,
@@ -603,6 +607,11 @@ at_status at_set_fuse(at_ctx *c, int32_t s)
     const int mf = max_fuse(c);
     if (s > mf) return fail(AT_ERR_ARG, "fuse_steps %d exceeds the limit %d of this grid", s, mf);
     c->fuse = s;
+    if (c->d.dim == 3) {   // 3D: the kernel variant follows the steps per launch
+        if (s == 2 && !at3_is_fused(c->variant))
+            c->variant = at3_variant_ok(&c->cfg, 15) ? 15 : 16;
+        if (s == 1) c->variant = at3_single_variant(&c->cfg, c->variant);
+    }
     return AT_OK;
 }
 
@@ -636,6 +645,8 @@ at_status at_set_variant(at_ctx *c, int32_t v)
             return fail(AT_ERR_ARG, "variant %d needs a tile width divisible by %d", v, p);
         c->d.fppt = p ? p : fused_ppt(c->d);
         c->fuse = std::min(c->fuse, max_fuse(c));
+    } else {
+        c->fuse = at3_is_fused(v) ? 2 : 1;   // 3D: two-step variants advance two steps per launch
     }
     c->variant = v;
     return AT_OK;
@@ -861,7 +872,7 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
     if (trial_steps < 1 || trial_steps > c->cfg.nsteps_max)
         return fail(AT_ERR_ARG, "trial_steps must be in 1..nsteps_max");
     const int mf = max_fuse(c);
-    // 1D: steps per launch; 3D: kernel variant (one step per launch)
+    // 1D: steps per launch; 3D: kernel variant (one or two steps per launch)
     std::vector<int> cands;
     if (c->d.dim == 1) {
         for (int s : {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 56, 64})
@@ -888,8 +899,12 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
             hipError_t e = clear_ring(c);
             if (e == hipSuccess) e = launch_copy(t1, u0, field_doubles(c), c->st);
             c->n = 0;
-            if (c->d.dim == 1) c->fuse = s;
-            else c->variant = s;
+            if (c->d.dim == 1) {
+                c->fuse = s;
+            } else {
+                c->variant = s;
+                c->fuse = at3_is_fused(s) ? 2 : 1;
+            }
             if (e == hipSuccess) e = hipEventRecord(e0, c->st);
             if (e == hipSuccess) st = at_run(c, t1, t2, trial_steps);
             if (e == hipSuccess && st == AT_OK) e = hipEventRecord(e1, c->st);
@@ -909,8 +924,12 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
     if (st) return st;
     AT_HIP(clear_ring(c));
     AT_HIP(hipStreamSynchronize(c->st));
-    if (c->d.dim == 1) c->fuse = best;
-    else c->variant = best;
+    if (c->d.dim == 1) {
+        c->fuse = best;
+    } else {
+        c->variant = best;
+        c->fuse = at3_is_fused(best) ? 2 : 1;
+    }
     if (chosen) *chosen = best;
     return AT_OK;
 }

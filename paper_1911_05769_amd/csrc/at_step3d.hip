@@ -576,6 +576,394 @@ __global__ __launch_bounds__(TX * TY, waves_for(MINW, NC)) void k_step3d_aligned
     march3d<TY, PF, NC, false>(A, A.uin, A.uout, A.slot0, pl, kdl, X0, Y0, Z0, Z1, bz0);
 }
 
+// ---------------------------------------------------------------------------
+// Two steps per launch (levels n -> n+2) for block shapes that are multiples
+// of the 64 x TY tile in x and y.
+//
+// A workgroup of 66 x (TY + 2) threads marches one 64 x TY tile through the
+// planes of a z-chunk.  Thread (ex, ey), ex in [-1, 64], ey in [-1, TY], owns
+// one point of the tile widened by one point on every side.  For each plane z
+// it computes level n+1 at that point exactly as the block that owns the
+// point would: with that block's delays, AT halo values across that block's
+// faces (section 2, Eqs. (1)-(2)) and the raw neighbour values elsewhere.
+// The threads of the 64 x TY interior then compute level n+2 one plane behind
+// (plane z - 1).  Their x/y neighbours come from an LDS plane of level n+1:
+// across a face of the tile's block it holds the neighbour block's own level
+// n+1 value when the step-(n+1) delay is 0 (computed here, redundantly) and
+// the AT value from the ring levels n+1-k, n-k when it is not.  Their z
+// neighbours come from the level-n+1 values of the planes before and after,
+// or from the ring the same way.  Every point update is the single-step
+// kernel's own sequence of operations, so two fused steps give the bits of
+// two single steps.
+//
+// LDS: level n of plane z on the tile widened by two (double-buffered, one
+// barrier per plane), level n+1 as the interior reads it (double-buffered),
+// and the delays of steps n and n+1 of the blocks around the tile for every
+// z-block row the chunk touches.  Each thread issues its own ring loads (AT
+// halos) for the next plane at the end of a plane, next to the field load of
+// the plane after next, so no load is waited on in the plane that issues it.
+// Levels n+1 and n+2 of the interior points on block faces are published to
+// the ring (slots n+1 and n+2).
+constexpr int kF2X = TX + 2;    // threads per row of the widened tile
+constexpr int kZB2 = 16;        // z-block rows the delay table of a fused chunk may span
+
+template <int TY, int NC>
+struct F2Lds {
+    double a[2][NC][TY + 4][TX + 4];     // level n of a plane, tile widened by two
+    double b[2][NC][TY + 2][TX + 2];     // level n+1 of a plane as the interior reads it
+    int8_t kd[kZB2][2][3][3][6];         // delays: z-block row, step, x / y block offset, face
+};
+
+template <int TY, int NC>
+constexpr size_t f2_lds() { return sizeof(F2Lds<TY, NC>); }
+
+__device__ __forceinline__ int fdiv32(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+__device__ __forceinline__ int pmod32(int a, int b) { const int r = a % b; return r < 0 ? r + b : r; }
+
+// an AT halo value in flight: levels n-k-? of a neighbour face, NC components
+template <int NC>
+struct F2Cross {
+    double a[NC], b[NC];
+    int k;          // 0: no substitution
+    int side;       // which neighbour it replaces (0 low, 1 high)
+};
+
+template <int TY, int NC>
+__global__ __launch_bounds__(kF2X * (TY + 2)) void k_step3d_f2(Step3D A)
+{
+    __shared__ F2Lds<TY, NC> sh;
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int t = ty * kF2X + tx;
+    constexpr int NT = kF2X * (TY + 2);
+    const int ex = tx - 1, ey = ty - 1;
+    const int nx = (int)A.nx, ny = (int)A.ny, nz = (int)A.nz;
+    const int Wx = A.Wx, Wy = A.Wy, Wz = A.Wz;
+    const int Px = A.Px, Py = A.Py, Pz = A.Pz;
+    const int X0 = blockIdx.x * TX, Y0 = blockIdx.y * TY;
+    const int Z0 = blockIdx.z * A.ZC;
+    const int Z1 = (Z0 + A.ZC < nz) ? Z0 + A.ZC : nz;
+    // offsets in doubles fit in 32 bits for the shapes this kernel accepts
+    // (NC x points and the ring below 2^31: at3_variant_ok), so addresses are
+    // a uniform base plus one 32-bit register
+    const int plane = nx * ny;
+    const int npt = (int)A.npt;
+    const int level = (int)A.level, bstride = (int)A.bstride;
+    const int ps0 = (int)A.psz[0], ps1 = (int)A.psz[1], ps2 = (int)A.psz[2];
+    const bool stale = A.stale != 0;
+    const int R = A.R;
+    const int sl0 = A.slot0;
+    const double *U0 = A.uin;
+
+    // this thread's point (ex, ey) of the widened tile and its block
+    const int x = wrap32(X0 + ex, nx), y = wrap32(Y0 + ey, ny);
+    const int col = y * nx + x;
+    const int bxp = x / Wx, byp = y / Wy;
+    const int lxp = x - bxp * Wx, lyp = y - byp * Wy;
+    const int bx = X0 / Wx, by = Y0 / Wy;                 // the tile's block in x and y
+    const int bxo = bxp == bx ? 0 : (ex < 0 ? -1 : 1);    // the point's block, relative
+    const int byo = byp == by ? 0 : (ey < 0 ? -1 : 1);
+    const bool interior = ex >= 0 && ex < TX && ey >= 0 && ey < TY;
+    const bool xlo = lxp == 0, xhi = lxp == Wx - 1;       // on its block's faces (x, y)
+    const bool ylo = lyp == 0, yhi = lyp == Wy - 1;
+    // rim points next to the interior across a face of the tile's block: that
+    // face (its level-n+1 slot then holds what the interior reads across it)
+    int rface = -1;
+    if (ey >= 0 && ey < TY) {
+        if (ex == -1 && X0 % Wx == 0) rface = 0;
+        if (ex == TX && (X0 + TX) % Wx == 0) rface = 1;
+    }
+    if (ex >= 0 && ex < TX) {
+        if (ey == -1 && Y0 % Wy == 0) rface = 2;
+        if (ey == TY && (Y0 + TY) % Wy == 0) rface = 3;
+    }
+    // the point of the outer ring (tile widened by two, minus the widened by
+    // one) this thread loads, if any: rows -2 and TY+1, then columns -2, TX+1
+    constexpr int NOUT = 2 * (TX + 4) + 2 * (TY + 2);
+    int ox = 0, oy = 0;
+    const bool has_out = t < NOUT;
+    if (has_out) {
+        if (t < 2 * (TX + 4)) {
+            oy = t < TX + 4 ? -2 : TY + 1;
+            ox = t % (TX + 4) - 2;
+        } else {
+            const int o2 = t - 2 * (TX + 4);
+            ox = o2 < TY + 2 ? -2 : TX + 1;
+            oy = o2 % (TY + 2) - 1;
+        }
+    }
+    // every thread issues the outer-ring load (those without an outer point
+    // reload their own), so the count of loads in flight is the same in every
+    // wave and every wait in the march can leave the newer loads in flight
+    const int ocol = has_out ? wrap32(Y0 + oy, ny) * nx + wrap32(X0 + ox, nx) : col;
+
+    // ---- delays of steps n and n+1 of the 3 x 3 blocks around the tile's
+    // block, for each z-block row of planes Z0-1 .. Z1
+    const int zb_first = fdiv32(Z0 - 1, Wz);
+    const int nzb = fdiv32(Z1, Wz) - zb_first + 1;        // <= kZB2 (host bounds ZC)
+    {
+        int8_t *kflat = &sh.kd[0][0][0][0][0];
+        for (int e = t; e < nzb * 108; e += NT) {
+            const int f = e % 6, yo1 = (e / 6) % 3, xo1 = (e / 18) % 3, s = (e / 54) & 1;
+            const int j = e / 108;
+            const int64_t b = ((int64_t)pmod32(zb_first + j, Pz) * Py + pmod32(by + yo1 - 1, Py)) *
+                                  Px + pmod32(bx + xo1 - 1, Px);
+            kflat[e] = A.delays[(A.n + s) * A.F + 6 * b + f];
+        }
+    }
+    // ring slot (offset in doubles) of level n + d, |d| <= L + 2 < R
+    auto slot = [&](int d) -> int {
+        int q = sl0 + d;
+        if (q < 0) q += R;
+        if (q >= R) q -= R;
+        return q * level;
+    };
+    // offsets of the faces this thread's ring reads use, picked once with
+    // constant indices (a per-lane index into the argument block would be a
+    // memory load); the neighbour blocks across its x / y faces
+    const int fo_x = (int)(xlo ? A.foff[1] : A.foff[0]);  // the x neighbour's face towards it
+    const int fo_y = (int)(ylo ? A.foff[3] : A.foff[2]);
+    const int fo_zl = (int)A.foff[5], fo_zh = (int)A.foff[4];
+    int fo_r = 0;                                         // rim: face rface ^ 1 of its block
+    if (rface == 0) fo_r = (int)A.foff[1];
+    if (rface == 1) fo_r = (int)A.foff[0];
+    if (rface == 2) fo_r = (int)A.foff[3];
+    if (rface == 3) fo_r = (int)A.foff[2];
+    const int cs_r = rface >= 2 ? ps1 : ps0;
+    // loads of an AT halo value: levels n+d-k and n+d-k-1 of the face at
+    // offset fo of block (qx, qy, qz), position pos (components cs apart)
+    auto cross_load = [&](F2Cross<NC> &cr, int k, int side, int d, int qx, int qy, int qz,
+                          int fo, int pos, int cs) {
+        cr.k = k;
+        cr.side = side;
+        if (k > 0) {
+            const int fb = ((qz * Py + qy) * Px + qx) * bstride + fo + pos;
+            const double *p0 = A.ring + (unsigned)(slot(d - k) + fb);
+            const double *p1 = A.ring + (unsigned)((stale ? slot(d - k) : slot(d - k - 1)) + fb);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) cr.a[c] = p0[(unsigned)(c * cs)];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) cr.b[c] = p1[(unsigned)(c * cs)];
+        }
+    };
+
+    auto zneighbour = [&](int bz, bool lo) -> int {
+        return lo ? (bz == 0 ? Pz - 1 : bz - 1) : (bz == Pz - 1 ? 0 : bz + 1);
+    };
+    // position of plane zi along z: wrapped z, block row (wrapped), local z,
+    // row of the delay table (recomputed where used: fewer values live)
+    struct PlaneZ { int zw, bz, lz, j; };
+    auto planez = [&](int zi) -> PlaneZ {
+        PlaneZ p;
+        p.zw = wrap32(zi, nz);
+        p.bz = p.zw / Wz;
+        p.lz = p.zw - p.bz * Wz;
+        p.j = fdiv32(zi, Wz) - zb_first;
+        return p;
+    };
+
+    F2Cross<NC> cx{}, cy{}, cz{}, cs{};
+    // the ring loads needed in the iteration of plane zi (p = its position,
+    // q = that of plane zi-1): the AT halos of level n at this thread's point
+    // of plane zi (x, y, z faces of the point's block); for a rim point, what
+    // the interior reads across the tile block's face at level n+1; for an
+    // interior point, the AT halo of level n+1 across a z face at plane zi-1
+    // (whose level n+2 it computes)
+    auto issue_cross = [&](int zi) {
+        cx.k = cy.k = cz.k = cs.k = 0;
+        const PlaneZ p = planez(zi);
+        const int8_t *kp = &sh.kd[p.j][0][bxo + 1][byo + 1][0];
+        if (xlo || xhi) {
+            const int qbx = xlo ? (bxp == 0 ? Px - 1 : bxp - 1) : (bxp == Px - 1 ? 0 : bxp + 1);
+            cross_load(cx, kp[xlo ? 0 : 1], xlo ? 0 : 1, 0, qbx, byp, p.bz, fo_x,
+                       p.lz * Wy + lyp, ps0);
+        }
+        if (ylo || yhi) {
+            const int qby = ylo ? (byp == 0 ? Py - 1 : byp - 1) : (byp == Py - 1 ? 0 : byp + 1);
+            cross_load(cy, kp[ylo ? 2 : 3], ylo ? 0 : 1, 0, bxp, qby, p.bz, fo_y,
+                       p.lz * Wx + lxp, ps1);
+        }
+        if (p.lz == 0 || p.lz == Wz - 1) {
+            const bool lo = p.lz == 0;
+            cross_load(cz, kp[lo ? 4 : 5], lo ? 0 : 1, 0, bxp, byp, zneighbour(p.bz, lo),
+                       lo ? fo_zl : fo_zh, lyp * Wx + lxp, ps2);
+        }
+        if (rface >= 0) {
+            const int pos = rface < 2 ? p.lz * Wy + lyp : p.lz * Wx + lxp;
+            cross_load(cs, sh.kd[p.j][1][1][1][rface], rface & 1, 1, bxp, byp, p.bz, fo_r, pos,
+                       cs_r);
+        } else if (interior && zi - 1 >= Z0) {
+            const PlaneZ q = planez(zi - 1);
+            if (!(q.lz == 0 || q.lz == Wz - 1)) return;
+            const bool lo = q.lz == 0;
+            cross_load(cs, sh.kd[q.j][1][1][1][lo ? 4 : 5], lo ? 0 : 1, 1, bx, by,
+                       zneighbour(q.bz, lo), lo ? fo_zl : fo_zh, lyp * Wx + lxp, ps2);
+        }
+    };
+
+    // ---- prologue: level n of planes Z0-2, Z0-1, Z0 at this point; plane
+    // Z0-1 (widened by two) into LDS; outer ring of plane Z0 in flight
+    double qm[NC], qc[NC], qa[NC], qb[NC], ov[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) qm[c] = U0[(unsigned)(c * npt + wrap32(Z0 - 2, nz) * plane + col)];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) qc[c] = U0[(unsigned)(c * npt + wrap32(Z0 - 1, nz) * plane + col)];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) qa[c] = U0[(unsigned)(c * npt + wrap32(Z0, nz) * plane + col)];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) ov[c] = U0[(unsigned)(c * npt + wrap32(Z0 - 1, nz) * plane + ocol)];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        sh.a[0][c][ey + 2][ex + 2] = qc[c];
+        if (has_out) sh.a[0][c][oy + 2][ox + 2] = ov[c];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) ov[c] = U0[(unsigned)(c * npt + wrap32(Z0, nz) * plane + ocol)];
+    __syncthreads();                                      // delay table ready
+    issue_cross(Z0 - 1);
+
+    const double c10 = A.c1[0], c11 = A.c1[1], c12 = A.c1[2];
+    const double c20 = A.c2[0], c21 = A.c2[1], c22 = A.c2[2];
+    const double dt = A.dt;
+    const int s1 = slot(1), s2 = slot(2);                 // ring slots of levels n+1, n+2
+    double h1[NC], h2[NC];                                // level n+1 of planes z-1, z-2
+#pragma unroll
+    for (int c = 0; c < NC; ++c) h1[c] = h2[c] = 0.0;
+
+    // publish a value of the tile's block at (lx, ly, lz) of block row bzb
+    auto publish = [&](int sl, int bzb, int lzb, const double (&v)[NC]) {
+        if (!(xlo || xhi || ylo || yhi || lzb == 0 || lzb == Wz - 1)) return;
+        const int base = sl + ((bzb * Py + by) * Px + bx) * bstride;
+        const int px = lzb * Wy + lyp, py = lzb * Wx + lxp, pz = lyp * Wx + lxp;
+        double *R0 = A.ring;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (xlo) R0[(unsigned)(base + (int)A.foff[0] + c * ps0 + px)] = v[c];
+            if (xhi) R0[(unsigned)(base + (int)A.foff[1] + c * ps0 + px)] = v[c];
+            if (ylo) R0[(unsigned)(base + (int)A.foff[2] + c * ps1 + py)] = v[c];
+            if (yhi) R0[(unsigned)(base + (int)A.foff[3] + c * ps1 + py)] = v[c];
+            if (lzb == 0) R0[(unsigned)(base + (int)A.foff[4] + c * ps2 + pz)] = v[c];
+            if (lzb == Wz - 1) R0[(unsigned)(base + (int)A.foff[5] + c * ps2 + pz)] = v[c];
+        }
+    };
+
+    // one plane z: qp holds level n of plane z+1 (complete), qn receives
+    // plane z+2.  The field and outer-ring loads are unconditional (in bounds
+    // past the chunk), so the wait counts are static; the ring loads of the
+    // next plane go out last.  (One body per iteration: the queue rotates by
+    // copies at the end of a plane, which wait only for the load issued at
+    // its start.)
+    auto body = [&](int z, double (&qp)[NC], double (&qn)[NC]) {
+        const int buf = (z - (Z0 - 1)) & 1;
+        {
+            const int o = wrap32(z + 2, nz) * plane + col;   // past Z1 + 1: unused, in bounds
+#pragma unroll
+            for (int c = 0; c < NC; ++c) qn[c] = U0[(unsigned)(c * npt + o)];
+        }
+        __syncthreads();
+        // ---- level n+1 at this point of plane z
+        double l1[NC];
+        {
+            const double ux = qc[0], uy = qc[1], uz = qc[2];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double u = qc[c];
+                double xl = sh.a[buf][c][ey + 2][ex + 1], xh = sh.a[buf][c][ey + 2][ex + 3];
+                double yl = sh.a[buf][c][ey + 1][ex + 2], yh = sh.a[buf][c][ey + 3][ex + 2];
+                double zl = qm[c], zh = qp[c];
+                if (cx.k > 0) {
+                    const double hv = at_h(cx.k, stale, cx.a[c], cx.b[c]);
+                    if (cx.side) xh = hv; else xl = hv;
+                }
+                if (cy.k > 0) {
+                    const double hv = at_h(cy.k, stale, cy.a[c], cy.b[c]);
+                    if (cy.side) yh = hv; else yl = hv;
+                }
+                if (cz.k > 0) {
+                    const double hv = at_h(cz.k, stale, cz.a[c], cz.b[c]);
+                    if (cz.side) zh = hv; else zl = hv;
+                }
+                const double D1x = (xh - xl) * c10, D2x = ((xh - 2.0 * u) + xl) * c20;
+                const double D1y = (yh - yl) * c11, D2y = ((yh - 2.0 * u) + yl) * c21;
+                const double D1z = (zh - zl) * c12, D2z = ((zh - 2.0 * u) + zl) * c22;
+                const double lap = (D2x + D2y) + D2z;
+                const double adv = (ux * D1x + uy * D1y) + uz * D1z;
+                l1[c] = u + dt * (A.kappa[c] * lap - adv);
+            }
+        }
+        // the step-(n+1) AT value of this plane (rim: what the interior reads
+        // here; interior: its z neighbour across a face)
+        double hs[NC];
+        const int hs_k = cs.k, hs_side = cs.side;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) hs[c] = hs_k > 0 ? at_h(hs_k, stale, cs.a[c], cs.b[c]) : 0.0;
+        // what the interior reads here at level n+1
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            sh.b[buf][c][ey + 1][ex + 1] = (rface >= 0 && hs_k > 0) ? hs[c] : l1[c];
+        const bool own = interior && z >= Z0 && z < Z1;
+        if (own) {
+            const PlaneZ p = planez(z);
+            publish(s1, p.bz, p.lz, l1);
+        }
+        // ---- level n+2 at this point of plane z-1
+        if (interior && z - 1 >= Z0) {
+            const int zz = z - 1;
+            const int pb = buf ^ 1;
+            double l2[NC];
+            const double ux = h1[0], uy = h1[1], uz = h1[2];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double u = h1[c];
+                const double xl = sh.b[pb][c][ey + 1][ex], xh = sh.b[pb][c][ey + 1][ex + 2];
+                const double yl = sh.b[pb][c][ey][ex + 1], yh = sh.b[pb][c][ey + 2][ex + 1];
+                double zl = h2[c], zh = l1[c];
+                if (hs_k > 0) {
+                    if (hs_side) zh = hs[c]; else zl = hs[c];
+                }
+                const double D1x = (xh - xl) * c10, D2x = ((xh - 2.0 * u) + xl) * c20;
+                const double D1y = (yh - yl) * c11, D2y = ((yh - 2.0 * u) + yl) * c21;
+                const double D1z = (zh - zl) * c12, D2z = ((zh - 2.0 * u) + zl) * c22;
+                const double lap = (D2x + D2y) + D2z;
+                const double adv = (ux * D1x + uy * D1y) + uz * D1z;
+                l2[c] = u + dt * (A.kappa[c] * lap - adv);
+            }
+            double *out = A.uout;
+            const int oo = zz * plane + col;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                __builtin_nontemporal_store(l2[c], &out[(unsigned)(c * npt + oo)]);
+            const PlaneZ p = planez(zz);
+            publish(s2, p.bz, p.lz, l2);
+        }
+        // ---- level n of plane z+1 into the other LDS buffer; the outer ring
+        // of plane z+2
+        if (z + 1 <= Z1) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                sh.a[buf ^ 1][c][ey + 2][ex + 2] = qp[c];
+                if (has_out) sh.a[buf ^ 1][c][oy + 2][ox + 2] = ov[c];
+            }
+        }
+        // rotate the plane queue (the load of plane z+2 was issued at the start
+        // of this plane) before the next loads go out
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            qm[c] = qc[c];
+            qc[c] = qp[c];
+            qp[c] = qn[c];
+            h2[c] = h1[c];
+            h1[c] = l1[c];
+        }
+        {
+            const int o = wrap32(z + 2, nz) * plane + ocol;  // past Z1: unused, in bounds
+#pragma unroll
+            for (int c = 0; c < NC; ++c) ov[c] = U0[(unsigned)(c * npt + o)];
+        }
+        if (z + 1 <= Z1) issue_cross(z + 1);                // ring loads of the next plane
+    };
+    for (int z = Z0 - 1; z <= Z1; ++z) body(z, qa, qb);
+}
+
 // Weakly-synchronous 3D run (emergent delays; paper section 5.2, Algorithm 2):
 // one workgroup per block, all blocks resident at once (cooperative launch).
 // Before step n, lanes 0..5 poll the level counters of the six face
@@ -848,29 +1236,74 @@ uint64_t at3_ring_level_doubles(const at_config *c)
     return (uint64_t)((int64_t)c->p[0] * c->p[1] * c->p[2] * block_stride(c));
 }
 
-int at3_max_fuse(const at_ctx *) { return 1; }
-
 // kernel variants the autotuner may choose from (tile rows, prefetch depth,
-// register budget); every variant performs the same operations
-int at3_variants() { return 15; }
+// register budget); every variant performs the same operations.  Variants
+// 15 and 16 advance two steps per launch (k_step3d_f2 with 8 and 4 tile rows).
+int at3_variants() { return 17; }
 static int k3_rows(int var)
 {
-    static const int r[15] = {8, 8, 4, 4, 16, 16, 8, 16, 4, 4, 8, 16, 8, 8, 16};
-    return r[var < 0 || var > 14 ? 0 : var];
+    static const int r[17] = {8, 8, 4, 4, 16, 16, 8, 16, 4, 4, 8, 16, 8, 8, 16, 8, 4};
+    return r[var < 0 || var > 16 ? 0 : var];
 }
 static bool is_direct(int var) { return var >= 9 && var <= 11; }
-static bool is_aligned(int var) { return (var >= 6 && var <= 8) || var >= 12; }
+static bool is_aligned(int var) { return (var >= 6 && var <= 8) || (var >= 12 && var <= 14); }
+bool at3_is_fused(int var) { return var == 15 || var == 16; }
+
+// LDS of the two-step kernel for TY rows and NC components (0: no build)
+static size_t f2_lds_bytes(int ty, int nc)
+{
+#define F2L(T)                                                                   \
+    switch (nc) {                                                                \
+    case 3: return f2_lds<T, 3>();                                               \
+    case 4: return f2_lds<T, 4>();                                               \
+    case 5: return f2_lds<T, 5>();                                               \
+    case 6: return f2_lds<T, 6>();                                               \
+    case 7: return f2_lds<T, 7>();                                               \
+    default: return 0;                                                           \
+    }
+    if (ty == 8) { F2L(8) }
+    if (ty == 4) { F2L(4) }
+#undef F2L
+    return 0;
+}
 
 // aligned variants need block widths that are multiples of the tile; tiled
-// variants need their LDS planes for NC components within a workgroup's LDS
+// variants need their LDS planes for NC components within a workgroup's LDS;
+// the two-step variants need both, and blocks at least 2 wide in z
 bool at3_variant_ok(const at_config *c, int var)
 {
-    if (var < 0 || var > 14) return false;
+    if (var < 0 || var > 16) return false;
     const int nc = ncomp(c);
+    const int64_t Wx = c->n[0] / c->p[0], Wy = c->n[1] / c->p[1], Wz = c->n[2] / c->p[2];
+    if (at3_is_fused(var)) {
+        // 32-bit offsets: NC fields and the ring (2L + 4 levels) below 2^31 doubles
+        const uint64_t npt = (uint64_t)c->n[0] * c->n[1] * c->n[2];
+        const uint64_t ring = (uint64_t)(2 * c->L + 4) * at3_ring_level_doubles(c);
+        if ((uint64_t)nc * npt >= ((uint64_t)1 << 31) || ring >= ((uint64_t)1 << 31)) return false;
+        const size_t lds = f2_lds_bytes(k3_rows(var), nc);
+        return lds > 0 && lds <= kMaxLds && Wx % TX == 0 && Wy % k3_rows(var) == 0 && Wz >= 2;
+    }
     if (!is_direct(var) && tile_lds(k3_rows(var), nc) > kMaxLds) return false;
     if (!is_aligned(var)) return true;
-    const int64_t Wx = c->n[0] / c->p[0], Wy = c->n[1] / c->p[1];
     return Wx % TX == 0 && Wy % k3_rows(var) == 0;
+}
+
+// steps per launch the configuration allows: 2 when a two-step variant has a
+// build for its shape
+int at3_max_fuse(const at_ctx *ctx)
+{
+    const at_config *c = at_ctx_cfg(ctx);
+    return (at3_variant_ok(c, 15) || at3_variant_ok(c, 16)) ? 2 : 1;
+}
+
+// the one-step variant used for a single step when a two-step variant is
+// selected (an odd step at the end of a run, at_step)
+int at3_single_variant(const at_config *c, int var)
+{
+    if (!at3_is_fused(var)) return var;
+    for (int v : {7, 6, 14, 12, 0})
+        if (at3_variant_ok(c, v)) return v;
+    return 0;
 }
 
 static void fill_step3d(at_ctx *ctx, const double *uin, double *uout, int64_t n0, int publish,
@@ -1016,12 +1449,59 @@ static bool launch3(int var, dim3 grid, dim3 block, hipStream_t st, const Step3D
 #undef K3_TILED
 }
 
+// two steps n0 -> n0 + 2 (k_step3d_f2)
+template <int TY, int NC>
+static bool launch_f2(dim3 grid, hipStream_t st, const Step3D &A)
+{
+    if constexpr (f2_lds<TY, NC>() <= kMaxLds) {
+        hipLaunchKernelGGL((k_step3d_f2<TY, NC>), grid, dim3(kF2X, TY + 2), 0, st, A);
+        return true;
+    }
+    return false;
+}
+
+static at_status at3_launch_f2(at_ctx *ctx, const double *uin, double *uout, int64_t n0)
+{
+    const at_config *c = at_ctx_cfg(ctx);
+    const int var = at_ctx_variant(ctx);
+    if (!at3_is_fused(var) || !at3_variant_ok(c, var))
+        return at_fail(AT_ERR_ARG, "two steps per launch need a two-step 3D variant (15, 16) "
+                                   "that fits this block shape");
+    Step3D A;
+    fill_step3d(ctx, uin, uout, n0, 1, A);
+    const int TYv = k3_rows(var);
+    const int64_t gx = A.nx / TX, gy = A.ny / TYv;
+    A.ZC = zchunk(A.nz, gx * gy);
+    // the chunk's planes Z0-1 .. Z1 span at most kZB2 z-block rows
+    if (A.ZC > (kZB2 - 3) * A.Wz) A.ZC = (kZB2 - 3) * A.Wz;
+    const int64_t gz = (A.nz + A.ZC - 1) / A.ZC;
+    const dim3 grid((unsigned)gx, (unsigned)gy, (unsigned)gz);
+    hipStream_t st = at_ctx_stream(ctx);
+    bool ok = false;
+#define F2N(T)                                                                   \
+    switch (A.nc) {                                                              \
+    case 3: ok = launch_f2<T, 3>(grid, st, A); break;                            \
+    case 4: ok = launch_f2<T, 4>(grid, st, A); break;                            \
+    case 5: ok = launch_f2<T, 5>(grid, st, A); break;                            \
+    case 6: ok = launch_f2<T, 6>(grid, st, A); break;                            \
+    case 7: ok = launch_f2<T, 7>(grid, st, A); break;                            \
+    default: break;                                                              \
+    }
+    if (TYv == 8) { F2N(8) } else { F2N(4) }
+#undef F2N
+    if (!ok) return at_fail(AT_ERR_ARG, "no two-step 3D build for this component count");
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return at_fail(AT_ERR_HIP, hipGetErrorString(e));
+    return AT_OK;
+}
+
 at_status at3_launch(at_ctx *ctx, const double *uin, double *uout, int64_t n0, int s, int publish)
 {
-    if (s != 1) return at_fail(AT_ERR_ARG, "3D stepper advances one step per launch");
+    if (s == 2) return at3_launch_f2(ctx, uin, uout, n0);
+    if (s != 1) return at_fail(AT_ERR_ARG, "3D stepper advances one or two steps per launch");
     Step3D A;
     fill_step3d(ctx, uin, uout, n0, publish, A);
-    const int var = at_ctx_variant(ctx);
+    const int var = at3_single_variant(at_ctx_cfg(ctx), at_ctx_variant(ctx));
     const int TYv = k3_rows(var);
     const int64_t gx = (A.nx + TX - 1) / TX, gy = (A.ny + TYv - 1) / TYv;
     A.ZC = zchunk(A.nz, gx * gy);
