@@ -269,7 +269,7 @@ int max_fuse_1d(const Derived &d)
         const int reg = kThreads * rg.ppt;
         if (rg.CH < std::min<int64_t>(reg / 2, d.N)) break;
         const int NT = (int)((reg - 1) / d.W + 2);
-        if (step1d_lds_bytes(d.order, s, NT, d.L + d.m - 1, rg.ppt) > 64 * 1024) break;
+        if (step1d_lds_bytes(d.order, s, NT, d.L + d.m - 1, rg.ppt, false) > 64 * 1024) break;
         best = s;
     }
     return best;
@@ -1208,7 +1208,8 @@ at_status batch_tables(at_batch *b, int slot, int s, double *const *u, double *c
         a.A2 = a.dt * (a.nu * a.c2);
         const int64_t nch = (d.N + rg.CH - 1) / rg.CH;
         for (int64_t c = 0; c < nch; ++c) T.push_back(make_int2(j, (int)c));
-        lds = std::max(lds, step1d_lds_bytes(b->order, s, a.NT, a.D, step1d_points_per_thread()));
+        lds = std::max(lds, step1d_lds_bytes(b->order, s, a.NT, a.D, step1d_points_per_thread(),
+                                             true));
     }
     if ((int64_t)T.size() > b->tbl_cap) return fail(AT_ERR_STATE, "batch block table overflow");
     AT_HIP(hipStreamSynchronize(b->st));
@@ -1473,7 +1474,7 @@ at_status at_batch_autotune(at_batch *b, double *const *u0, double *const *t1,
     if (b->n != 0) return fail(AT_ERR_STATE, "autotune needs a batch at step 0");
     if (trial_steps < 1 || trial_steps > b->nsteps_max)
         return fail(AT_ERR_ARG, "trial_steps must be in 1..nsteps_max");
-    static const int cands[] = {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32};
+    static const int cands[] = {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 56, 64};
     hipEvent_t e0, e1;
     AT_HIP(hipEventCreate(&e0));
     AT_HIP(hipEventCreate(&e1));

@@ -117,7 +117,7 @@ hipError_t launch_delays(int8_t *out, int64_t nsteps, int64_t F, int L, int m, i
 hipError_t launch_fill(double *p, int64_t n, double v, hipStream_t st);
 hipError_t launch_poison(double *ring, int64_t R, int64_t lev, int s0, int nlive, hipStream_t st);
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
-size_t step1d_lds_bytes(int order, int s, int NT, int D, int ppt);
+size_t step1d_lds_bytes(int order, int s, int NT, int D, int ppt, bool dense);
 int step1d_points_per_thread();
 int step1d_plain_points_per_thread();
 hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, bool fma, int ppt,

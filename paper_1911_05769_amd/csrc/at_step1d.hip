@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
 // computes recorded beside them, no step waits on a global load.
 // FUSED = false: exactly one step per launch (delays and delayed levels read
 // from global memory where used; no LDS edge history)
-template <int ORDER, bool LINEAR, bool FMA, bool FUSED = true, int PPT = kPPT>
+template <int ORDER, bool LINEAR, bool FMA, bool FUSED = true, int PPT = kPPT, bool DENSE = false>
 __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chunk)
 {
     constexpr int H = ORDER / 2;
@@ -278,6 +278,9 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     // latency overlaps theirs.
     const int D = a.D;
     int8_t *kd = reinterpret_cast<int8_t *>(eh + (size_t)(D + S - 1) * a.NT * 2 * H);
+    // AT halo values of the region's tile faces, one step at a time
+    // (double-buffered): [2][NT][2][H], after the delay bytes
+    double *hal = eh + (size_t)(D + S - 1) * a.NT * 2 * H + ((size_t)S * a.NT * 2 + 7) / 8;
     int64_t tb = floordiv(G0, a.W) % a.P;
     if (tb < 0) tb += a.P;
     const int nk = FUSED ? S * a.NT * 2 : 0;
@@ -327,6 +330,7 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
             const int64_t at = eh_src(e);
             if (at >= 0) eh[e] = a.ring[at];
         }
+        if (DENSE) __syncthreads();   // the dense halo table reads them before step 0's barrier
     }
 
     const int rp0 = tid * PPT;
@@ -370,6 +374,27 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
             buf[tid * 2 * H + q] = w[H + q];
             buf[tid * 2 * H + H + q] = w[PPT + q];
         }
+        // ---- DENSE (regions holding many tile edges, as in the batched form):
+        // the AT halo values of every tile face of the region for this step
+        // (section 2, Eqs. (1)-(2)), one lane per (tile, side, point) instead of
+        // a divergent branch in every edge thread; they read only levels below
+        // n (k >= 1), all recorded before the previous barrier
+        double *halt = hal + (t & 1) * (a.NT * 2 * H);
+        if constexpr (FUSED && DENSE) {
+            for (int e = tid; e < a.NT * 2 * H; e += kThreads) {
+                const int q = e % H, side = (e / H) & 1, tl = e / (2 * H);
+                const int stl = side == 0 ? tl - 1 : tl + 1;     // the tile the values come from
+                const int kk = kd[(t * a.NT + tl) * 2 + side];
+                if (kk > 0 && stl >= 0 && stl < a.NT) {
+                    double vv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int jj = 0; jj < M; ++jj)
+                        if (jj == 0 || !a.stale)
+                            vv[jj] = eh[(((t - kk - jj + D) * a.NT + stl) * 2 + (1 - side)) * H + q];
+                    halt[e] = extrap<FMA>(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
+                }
+            }
+        }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < H; ++q) {
@@ -387,28 +412,42 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
                 if (lo_edge && tid > 0) kl = krow[2 * tp0 + 0];
                 if (hi_edge) kr = krow[2 * tp0 + 1];
             }
+            if constexpr (FUSED && DENSE) {
 #pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                const int kk = side == 0 ? kl : kr;
-                if (kk > 0) {
-                    const int stl = side == 0 ? tl0 - 1 : tl0 + 1;
-                    const int64_t stp = side == 0 ? tpl : tpr;
-                    const int sside = 1 - side;
+                for (int side = 0; side < 2; ++side) {
+                    if ((side == 0 ? kl : kr) > 0) {
 #pragma unroll
-                    for (int q = 0; q < H; ++q) {
-                        double vv[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-                        for (int jj = 0; jj < M; ++jj) {
-                            if (jj == 0 || !a.stale) {
-                                const int64_t lev = n - kk - jj;
-                                vv[jj] = FUSED
-                                    ? eh[((((int)(lev - a.n0) + D) * a.NT + stl) * 2 + sside) * H + q]
-                                    : a.ring[((ring_slot(a, lev - a.n0) * a.P + stp) * 2 + sside) * H + q];
-                            }
+                        for (int q = 0; q < H; ++q) {
+                            const double hv = halt[(tl0 * 2 + side) * H + q];
+                            if (side == 0) w[q] = hv;
+                            else w[PPT + H + q] = hv;
                         }
-                        const double hv = extrap<FMA>(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
-                        if (side == 0) w[q] = hv;
-                        else w[PPT + H + q] = hv;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    const int kk = side == 0 ? kl : kr;
+                    if (kk > 0) {
+                        const int stl = side == 0 ? tl0 - 1 : tl0 + 1;
+                        const int64_t stp = side == 0 ? tpl : tpr;
+                        const int sside = 1 - side;
+#pragma unroll
+                        for (int q = 0; q < H; ++q) {
+                            double vv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                            for (int jj = 0; jj < M; ++jj) {
+                                if (jj == 0 || !a.stale) {
+                                    const int64_t lev = n - kk - jj;
+                                    vv[jj] = FUSED
+                                        ? eh[((((int)(lev - a.n0) + D) * a.NT + stl) * 2 + sside) * H + q]
+                                        : a.ring[((ring_slot(a, lev - a.n0) * a.P + stp) * 2 + sside) * H + q];
+                                }
+                            }
+                            const double hv = extrap<FMA>(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
+                            if (side == 0) w[q] = hv;
+                            else w[PPT + H + q] = hv;
+                        }
                     }
                 }
             }
@@ -475,7 +514,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d_aligned_batch(const Step1D 
         a.uin = a.uout;
         a.uout = const_cast<double *>(t);
     }
-    step1d_aligned_body<ORDER, LINEAR, FMA>(a, e.y);
+    step1d_aligned_body<ORDER, LINEAR, FMA, true, kPPT, true>(a, e.y);
 }
 
 }  // namespace
@@ -483,13 +522,14 @@ __global__ __launch_bounds__(kThreads) void k_step1d_aligned_batch(const Step1D 
 int step1d_points_per_thread() { return kPPT; }
 int step1d_plain_points_per_thread() { return kPPTPlain; }
 
-size_t step1d_lds_bytes(int order, int s, int NT, int D, int ppt)
+size_t step1d_lds_bytes(int order, int s, int NT, int D, int ppt, bool dense)
 {
     const int H = order / 2;
     const size_t stage = (size_t)kThreads * ppt + kThreads;
-    // exchange buffers, edge history of D + s - 1 levels, delays (bytes)
+    // exchange buffers, edge history of D + s - 1 levels, delays (bytes), and
+    // for the batched kernel's dense form the AT halo table [2][NT][2][H]
     const size_t steps = (size_t)2 * kThreads * 2 * H + (size_t)(D + s - 1) * NT * 2 * H +
-                         ((size_t)s * NT * 2 + 7) / 8;
+                         ((size_t)s * NT * 2 + 7) / 8 + (dense ? (size_t)2 * NT * 2 * H : 0);
     return 8 * (stage > steps ? stage : steps);
 }
 
@@ -497,7 +537,7 @@ hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, 
                          int64_t nblocks, hipStream_t st)
 {
     const bool plain = aligned && a.s == 1 && ppt == kPPTPlain;
-    size_t lds = step1d_lds_bytes(order, a.s, a.NT, a.D, aligned ? ppt : kPPT);
+    size_t lds = step1d_lds_bytes(order, a.s, a.NT, a.D, aligned ? ppt : kPPT, false);
     if (plain) {
         const size_t stage = (size_t)kThreads * kPPTPlain + kThreads;
         const size_t xch = (size_t)2 * kThreads * order;
