@@ -141,14 +141,15 @@ def bench_c2(args, torch, at, I, fuse=None, label="main", arith=0):
     # issue-rate ceiling for this instruction mix: 39.3 T FP64 instructions/s
     # (a diagnostic; the roofline's peak is the published 78.6 TFLOP/s)
     issue_ceiling = FP64_ISSUE_TINSTR * fl / ins
-    res = dict(wl=wl, s=s, wall=wall, ms_per_step=wall * 1e3 / args.steps, run_ms=run_ms,
+    ppt = {1: 16, 2: 8, 3: 4}.get(st.variant, 16)
+    res = dict(wl=wl, s=s, ppt=ppt, wall=wall, ms_per_step=wall * 1e3 / args.steps, run_ms=run_ms,
                value=N * wl.nsteps * args.steps / wall, ms_launch=ms_launch, gbps=gbps,
                tflops=tflops, issue_ceiling=issue_ceiling, arith=arith, launches=launches,
                bytes_launch=bytes_launch, u0=wl.u0,
                delays=st.delays(), uT=u)
-    eprint("[%s] fuse %d: %.3f ms/run, %.4g updates/s, kernel %.1f us/launch, %.0f GB/s, "
-           "%.2f TFLOP/s" % (label, s, res["ms_per_step"], res["value"], ms_launch * 1e3, gbps,
-                             tflops))
+    eprint("[%s] fuse %d, %d points/thread: %.3f ms/run, %.4g updates/s, kernel %.1f us/launch, "
+           "%.0f GB/s, %.2f TFLOP/s" % (label, s, ppt, res["ms_per_step"], res["value"],
+                                        ms_launch * 1e3, gbps, tflops))
     return res
 
 
@@ -337,9 +338,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": main_res["wl"].name, "n": main_res["wl"].n[0],
                    "p": main_res["wl"].p[0], "order": 4, "L": 4, "nsteps": 2000,
-                   "fuse_steps": main_res["s"], "arith": "exact order, no contraction",
+                   "fuse_steps": main_res["s"], "points_per_thread": main_res["ppt"],
+                   "arith": "exact order, no contraction",
                    "kernel": ("k_step1d_plain<4,false,false>" if main_res["s"] == 1
-                              else "k_step1d_aligned<4,false,false,16>")},
+                              else "k_step1d_aligned<4,false,false,%d>" % main_res["ppt"])},
         "roofline": rl,
         "roofline_other": rl_other,
         "timing": dict(spread(main_res["run_ms"]), clock="HIP events around each 2000-step run"),
@@ -462,6 +464,7 @@ def bench_batched(args, torch, at, I):
     algo = sum(algo_bytes_1d(w.n[0], w.p[0], w.order, w.L, w.dist, 1) for w in wls) * nst
     res.update({
         "value": upd / k3, "unit": "grid-point updates/s", "fuse_steps": s,
+        "points_per_thread": {0: 16, 1: 16, 2: 8, 3: 4}[b.variant],
         "ms_graph_run": round(k3 * 1e3, 3),
         "ms_per_instance_plain": round(k1 * 1e3, 3),
         "ms_one_launch_per_step": round(k2 * 1e3, 3),
@@ -470,8 +473,8 @@ def bench_batched(args, torch, at, I):
         "one_launch_per_step_hbm_gbps": round(algo / k2 / 1e9, 1),
         "bitwise_equal_to_per_instance": bool(same)})
     eprint("[batched] %d instances, %d points: per-instance %.1f ms, one launch/step %.1f ms, "
-           "fused(s=%d)+graph %.2f ms (%.3g updates/s)" % (len(wls), pts, k1 * 1e3, k2 * 1e3, s,
-                                                           k3 * 1e3, upd / k3))
+           "fused(s=%d, variant %d)+graph %.2f ms (%.3g updates/s)" %
+           (len(wls), pts, k1 * 1e3, k2 * 1e3, s, b.variant, k3 * 1e3, upd / k3))
     return res
 
 

@@ -208,12 +208,14 @@ at_status at_set_graph(at_ctx *ctx, int32_t use_graph);
 #define AT_DEBUG_POISON_RING 1
 at_status at_set_debug(at_ctx *ctx, int32_t flags);
 
-/* Choose steps-per-launch s (1D) or the kernel variant (3D, including the
- * two-step variants) -- nothing that
+/* Choose the launch shape -- 1D: points per thread (the variant, 16, 8 or 4
+ * among those dividing the tile width) together with steps per launch s; 3D:
+ * the kernel variant (including the two-step variants) -- nothing that
  * changes results -- by timing `trial_steps` steps from u0 for each
  * candidate; requires n == 0 and leaves the context at n = 0 with the ring
  * cleared.  u0 is not modified; t1 and t2 are two scratch fields.
- * Synchronises the stream.  *chosen receives s (1D) or the variant (3D). */
+ * Synchronises the stream.  *chosen receives s (1D) or the variant (3D);
+ * at_query returns both. */
 at_status at_autotune(at_ctx *ctx, const double *u0, double *t1, double *t2,
                       int32_t trial_steps, int32_t *chosen);
 
@@ -234,8 +236,10 @@ at_status at_autotune(at_ctx *ctx, const double *u0, double *t1, double *t2,
  * divisible by it, AT_ERR_ARG otherwise); every choice gives the same bits. */
 at_status at_set_variant(at_ctx *ctx, int32_t variant);
 
-/* Current step n, steps per launch in use, ring levels R. */
-at_status at_query(const at_ctx *ctx, int64_t *n, int32_t *fuse_steps, int32_t *ring_levels);
+/* Current step n, steps per launch in use, ring levels R, kernel variant
+ * (at_set_variant; chosen by at_autotune).  Any output may be NULL. */
+at_status at_query(const at_ctx *ctx, int64_t *n, int32_t *fuse_steps, int32_t *ring_levels,
+                   int32_t *variant);
 
 /* Copy the delay array (int8[nsteps_max][F], after the clamp) to host memory.
  * Synchronous. */
@@ -314,11 +318,20 @@ at_status at_batch_run(at_batch *b, double *const *u_dev, double *const *scratch
  * (asynchronous; the caller reloads the fields). */
 at_status at_batch_reset(at_batch *b);
 
-/* Shared step counter, steps per launch in use and its upper limit. */
-at_status at_batch_query(const at_batch *b, int64_t *n, int32_t *fuse_steps, int32_t *max_fuse);
+/* Shared step counter, steps per launch in use and its upper limit (for the
+ * points per thread in use), and the batch's variant. */
+at_status at_batch_query(const at_batch *b, int64_t *n, int32_t *fuse_steps, int32_t *max_fuse,
+                         int32_t *variant);
 
-/* Choose the batch's steps per launch by timing (same contract as
- * at_autotune, per batch). */
+/* Points per thread of the batched kernel: 0 (default) and 1: 16, 2: 8,
+ * 3: 4.  Fewer points per thread make shorter regions (more workgroups, more
+ * redundant rim work per point).  Steps per launch are lowered to the limit
+ * of the new layout if needed.  Every choice gives the same bits. */
+at_status at_batch_set_variant(at_batch *b, int32_t variant);
+
+/* Choose the batch's points per thread and steps per launch by timing (same
+ * contract as at_autotune, per batch); *chosen receives the steps per
+ * launch, at_batch_query both. */
 at_status at_batch_autotune(at_batch *b, double *const *u_dev, double *const *t1,
                             double *const *t2, int32_t trial_steps, int32_t *chosen);
 at_status at_batch_set_fuse(at_batch *b, int32_t fuse_steps);

@@ -91,7 +91,7 @@ SIGNATURES = {
     "at_set_variant": (ctypes.c_int, [_P, ctypes.c_int32]),
     "at_set_graph": (ctypes.c_int, [_P, ctypes.c_int32]),
     "at_set_debug": (ctypes.c_int, [_P, ctypes.c_int32]),
-    "at_query": (ctypes.c_int, [_P, _P, _P, _P]),
+    "at_query": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "at_delays_copy": (ctypes.c_int, [_P, _P]),
     "at_snapshot_bytes": (ctypes.c_int, [_P, _P]),
     "at_snapshot": (ctypes.c_int, [_P, _P, _P]),
@@ -107,7 +107,8 @@ SIGNATURES = {
     "at_batch_autotune": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int32, _P]),
     "at_batch_set_fuse": (ctypes.c_int, [_P, ctypes.c_int32]),
     "at_batch_reset": (ctypes.c_int, [_P]),
-    "at_batch_query": (ctypes.c_int, [_P, _P, _P, _P]),
+    "at_batch_query": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "at_batch_set_variant": (ctypes.c_int, [_P, ctypes.c_int32]),
 }
 
 
@@ -337,10 +338,18 @@ class Stepper:
         _check(lib().at_set_debug(self._ctx, int(flags)), "at_set_debug")
 
     def query(self):
+        """(step n, steps per launch, ring levels R)"""
         n, s, R = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().at_query(self._ctx, ctypes.byref(n), ctypes.byref(s), ctypes.byref(R)),
-               "at_query")
+        _check(lib().at_query(self._ctx, ctypes.byref(n), ctypes.byref(s), ctypes.byref(R),
+                              None), "at_query")
         return int(n.value), int(s.value), int(R.value)
+
+    @property
+    def variant(self) -> int:
+        """Kernel variant in use (1D: 0 automatic, 1/2/3 = 16/8/4 points per thread)."""
+        v = ctypes.c_int32()
+        _check(lib().at_query(self._ctx, None, None, None, ctypes.byref(v)), "at_query")
+        return int(v.value)
 
     @property
     def n(self) -> int:
@@ -468,7 +477,19 @@ class Batch:
         _check(lib().at_batch_reset(self._h), "at_batch_reset")
 
     def query(self):
+        """(shared step n, steps per launch, its limit)"""
         n, s, m = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib().at_batch_query(self._h, ctypes.byref(n), ctypes.byref(s), ctypes.byref(m)),
-               "at_batch_query")
+        _check(lib().at_batch_query(self._h, ctypes.byref(n), ctypes.byref(s), ctypes.byref(m),
+                                    None), "at_batch_query")
         return int(n.value), int(s.value), int(m.value)
+
+    @property
+    def variant(self) -> int:
+        """Points-per-thread variant (0/1: 16, 2: 8, 3: 4)."""
+        v = ctypes.c_int32()
+        _check(lib().at_batch_query(self._h, None, None, None, ctypes.byref(v)),
+               "at_batch_query")
+        return int(v.value)
+
+    def set_variant(self, v: int):
+        _check(lib().at_batch_set_variant(self._h, int(v)), "at_batch_set_variant")

@@ -652,12 +652,13 @@ at_status at_set_variant(at_ctx *c, int32_t v)
     return AT_OK;
 }
 
-at_status at_query(const at_ctx *c, int64_t *n, int32_t *fuse, int32_t *R)
+at_status at_query(const at_ctx *c, int64_t *n, int32_t *fuse, int32_t *R, int32_t *variant)
 {
     if (!c) return fail(AT_ERR_ARG, "null context");
     if (n) *n = c->n;
     if (fuse) *fuse = c->fuse;
     if (R) *R = c->lay.R;
+    if (variant) *variant = c->variant;
     return AT_OK;
 }
 
@@ -871,15 +872,25 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
     if (c->cfg.record) return fail(AT_ERR_STATE, "autotune is not available in record mode");
     if (trial_steps < 1 || trial_steps > c->cfg.nsteps_max)
         return fail(AT_ERR_ARG, "trial_steps must be in 1..nsteps_max");
-    const int mf = max_fuse(c);
-    // 1D: steps per launch; 3D: kernel variant (one or two steps per launch)
-    std::vector<int> cands;
+    // 1D: (points per thread, steps per launch) pairs, the points per thread
+    // as the variant (1, 2, 3: 16, 8, 4; those dividing the tile width);
+    // 3D: the kernel variant (one or two steps per launch)
+    std::vector<std::pair<int, int>> cands;       // (variant, steps per launch)
     if (c->d.dim == 1) {
-        for (int s : {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 56, 64})
-            if (s <= mf) cands.push_back(s);
+        const Derived keep = c->d;
+        for (int v = 1; v <= 3; ++v) {
+            const int p = v == 1 ? 16 : (v == 2 ? 8 : 4);
+            if (c->d.W % p != 0) continue;
+            c->d.fppt = p;
+            const int mf = max_fuse(c);
+            for (int s : {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 56, 64})
+                if (s <= mf && (s > 1 || v == 1)) cands.push_back({v, s});   // one step: one kernel
+        }
+        c->d = keep;
+        if (cands.empty()) cands.push_back({c->variant, 1});
     } else {
         for (int v = 0; v < at3_variants(); ++v)
-            if (at3_variant_ok(&c->cfg, v)) cands.push_back(v);
+            if (at3_variant_ok(&c->cfg, v)) cands.push_back({v, at3_is_fused(v) ? 2 : 1});
     }
     hipEvent_t e0, e1;
     AT_HIP(hipEventCreate(&e0));
@@ -888,23 +899,26 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
         return fail(AT_ERR_HIP, "at_autotune: hipEventCreate failed");
     }
     float best_ms = 1e30f;
-    int best = cands[0];
+    std::pair<int, int> best = cands[0];
     const int keep_graph = c->use_graph;
     c->use_graph = 0;                         // time the launches themselves
     at_status st = AT_OK;
+    // select a candidate: the variant (1D: points per thread) and steps per launch
+    auto choose = [&](std::pair<int, int> vs) {
+        if (c->d.dim == 1) {
+            const int p = vs.first == 1 ? 16 : (vs.first == 2 ? 8 : 4);
+            c->d.fppt = p;
+        }
+        c->variant = vs.first;
+        c->fuse = vs.second;
+    };
     for (size_t i = 0; i < cands.size() && st == AT_OK; ++i) {
-        const int s = cands[i];
         float ms_best = 1e30f;
         for (int rep = 0; rep < 2 && st == AT_OK; ++rep) {
             hipError_t e = clear_ring(c);
             if (e == hipSuccess) e = launch_copy(t1, u0, field_doubles(c), c->st);
             c->n = 0;
-            if (c->d.dim == 1) {
-                c->fuse = s;
-            } else {
-                c->variant = s;
-                c->fuse = at3_is_fused(s) ? 2 : 1;
-            }
+            choose(cands[i]);
             if (e == hipSuccess) e = hipEventRecord(e0, c->st);
             if (e == hipSuccess) st = at_run(c, t1, t2, trial_steps);
             if (e == hipSuccess && st == AT_OK) e = hipEventRecord(e1, c->st);
@@ -915,22 +929,17 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
                 st = fail(AT_ERR_HIP, "at_autotune: %s", hipGetErrorString(e));
             ms_best = std::min(ms_best, ms);
         }
-        if (st == AT_OK && ms_best < best_ms * 0.98f) { best_ms = ms_best; best = s; }
+        if (st == AT_OK && ms_best < best_ms * 0.98f) { best_ms = ms_best; best = cands[i]; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->use_graph = keep_graph;
     c->n = 0;
     if (st) return st;
+    choose(best);
     AT_HIP(clear_ring(c));
     AT_HIP(hipStreamSynchronize(c->st));
-    if (c->d.dim == 1) {
-        c->fuse = best;
-    } else {
-        c->variant = best;
-        c->fuse = at3_is_fused(best) ? 2 : 1;
-    }
-    if (chosen) *chosen = best;
+    if (chosen) *chosen = c->d.dim == 1 ? best.second : best.first;
     return AT_OK;
 }
 
@@ -1125,6 +1134,9 @@ struct at_batch {
     std::vector<int64_t> ring_doubles;
     int64_t nsteps_max = 0;   // smallest over the instances
     int max_fuse = 1, fuse = 1;
+    int ppt = 16;             // points per thread of the batched kernel (16, 8 or 4)
+    int variant = 0;          // 0 automatic (16), 1, 2, 3: 16, 8, 4 points per thread
+    int mf_ppt[3] = {1, 1, 1};   // steps-per-launch limit for 16, 8, 4 points per thread
     int64_t n = 0;
     // device tables (two slots: the run's s and its tail)
     Step1D *desc_dev[2] = {nullptr, nullptr};
@@ -1142,7 +1154,7 @@ struct at_batch {
     bool has_graph = false;
     hipGraphExec_t gexec = nullptr;
     int64_t g_n0 = -1, g_nsteps = -1;
-    int g_fuse = 0;
+    int g_fuse = 0, g_ppt = 0;
     uint64_t g_key = 0;
 };
 
@@ -1168,17 +1180,19 @@ void drop_graph(at_batch *b)
 at_status batch_tables(at_batch *b, int slot, int s, double *const *u, double *const *scr,
                        uint64_t key)
 {
-    const uint64_t k2 = key ^ ((uint64_t)s * 0x9E3779B97F4A7C15ULL);
+    const uint64_t k2 = key ^ ((uint64_t)s * 0x9E3779B97F4A7C15ULL) ^
+                        ((uint64_t)b->ppt * 0xD1B54A32D192ED03ULL);
     if (b->slot_s[slot] == s && b->slot_key[slot] == k2) return AT_OK;
     drop_graph(b);    // a cached graph reads these tables
-    const int reg = kThreads * step1d_points_per_thread();
+    const int reg = kThreads * b->ppt;
     std::vector<Step1D> &D = b->hdesc[slot];
     std::vector<int2> &T = b->htbl[slot];
     D.resize(b->count);
     T.clear();
     size_t lds = 0;
     for (int j = 0; j < b->count; ++j) {
-        const Derived &d = b->d[j];
+        Derived d = b->d[j];
+        d.fppt = b->ppt;
         const Region1D rg = region_1d(d, s, false);
         Step1D &a = D[j];
         a.uin = u[j];
@@ -1208,8 +1222,7 @@ at_status batch_tables(at_batch *b, int slot, int s, double *const *u, double *c
         a.A2 = a.dt * (a.nu * a.c2);
         const int64_t nch = (d.N + rg.CH - 1) / rg.CH;
         for (int64_t c = 0; c < nch; ++c) T.push_back(make_int2(j, (int)c));
-        lds = std::max(lds, step1d_lds_bytes(b->order, s, a.NT, a.D, step1d_points_per_thread(),
-                                             true));
+        lds = std::max(lds, step1d_lds_bytes(b->order, s, a.NT, a.D, b->ppt, true));
     }
     if ((int64_t)T.size() > b->tbl_cap) return fail(AT_ERR_STATE, "batch block table overflow");
     AT_HIP(hipStreamSynchronize(b->st));
@@ -1235,8 +1248,8 @@ at_status batch_launches(at_batch *b, int64_t n0, int64_t nsteps, double *const 
         const int s = (int)std::min<int64_t>(b->fuse, nsteps - done);
         const int slot = s == b->slot_s[0] ? 0 : 1;
         AT_HIP(launch_step1d_batch(b->desc_dev[slot], b->tbl_dev[slot], b->slot_blocks[slot],
-                                   b->order, b->linear, b->fma, n0 + done, flip, b->slot_lds[slot],
-                                   stream));
+                                   b->order, b->linear, b->fma, b->ppt, n0 + done, flip,
+                                   b->slot_lds[slot], stream));
         flip ^= 1;
         done += s;
     }
@@ -1253,7 +1266,7 @@ extern "C" {
 static at_status batch_layout(const at_config *cfgs, int32_t count, std::vector<Derived> &ds,
                               std::vector<uint64_t> &off_delays, std::vector<uint64_t> &off_ring,
                               std::vector<int> &Rs, uint64_t &off_desc, uint64_t &off_tbl,
-                              int64_t &tbl_cap, int &smax, uint64_t &total)
+                              int64_t &tbl_cap, int &smax, int (&mf_ppt)[3], uint64_t &total)
 {
     if (!cfgs || count < 1) return fail(AT_ERR_ARG, "batch needs at least one configuration");
     ds.resize(count);
@@ -1275,6 +1288,18 @@ static at_status batch_layout(const at_config *cfgs, int32_t count, std::vector<
                         (long long)ds[j].W, step1d_points_per_thread());
         smax = std::min(smax, max_fuse_1d(ds[j]));
     }
+    // steps-per-launch limit for each points-per-thread choice (16 gives the
+    // largest regions, so the rings sized for it serve every choice)
+    const int ppts[3] = {16, 8, 4};
+    for (int i = 0; i < 3; ++i) {
+        mf_ppt[i] = kMaxFuse;
+        for (int j = 0; j < count; ++j) {
+            Derived d = ds[j];
+            d.fppt = ppts[i];
+            mf_ppt[i] = std::min(mf_ppt[i], max_fuse_1d(d));
+        }
+        mf_ppt[i] = std::min(mf_ppt[i], smax);
+    }
     uint64_t off = 0;
     tbl_cap = 0;
     for (int j = 0; j < count; ++j) {
@@ -1284,8 +1309,12 @@ static at_status batch_layout(const at_config *cfgs, int32_t count, std::vector<
         off_ring[j] = off;
         off = align_up(off + 8ull * (uint64_t)Rs[j] * (uint64_t)ds[j].P * 2 * ds[j].h);
         int64_t chmin = ds[j].N;
-        for (int s = 1; s <= smax; ++s)
-            chmin = std::min<int64_t>(chmin, region_1d(ds[j], s, false).CH);
+        for (int i = 0; i < 3; ++i) {
+            Derived d = ds[j];
+            d.fppt = ppts[i];
+            for (int s = 1; s <= mf_ppt[i]; ++s)
+                chmin = std::min<int64_t>(chmin, region_1d(d, s, false).CH);
+        }
         tbl_cap += (ds[j].N + chmin - 1) / chmin;
     }
     off_desc = off;
@@ -1304,8 +1333,8 @@ at_status at_batch_workspace_bytes(const at_config *cfgs, int32_t count, uint64_
     std::vector<int> Rs;
     uint64_t odesc, otbl, total;
     int64_t cap;
-    int smax;
-    at_status st = batch_layout(cfgs, count, ds, od, orr, Rs, odesc, otbl, cap, smax, total);
+    int smax, mfp[3];
+    at_status st = batch_layout(cfgs, count, ds, od, orr, Rs, odesc, otbl, cap, smax, mfp, total);
     if (st) return st;
     *bytes = total;
     return AT_OK;
@@ -1321,8 +1350,8 @@ at_status at_batch_init(const at_config *cfgs, int32_t count, void *workspace,
     std::vector<int> Rs;
     uint64_t odesc, otbl, total;
     int64_t cap;
-    int smax;
-    at_status st = batch_layout(cfgs, count, ds, od, orr, Rs, odesc, otbl, cap, smax, total);
+    int smax, mfp[3];
+    at_status st = batch_layout(cfgs, count, ds, od, orr, Rs, odesc, otbl, cap, smax, mfp, total);
     if (st) return st;
     if (!workspace || ((uintptr_t)workspace) % kAlign)
         return fail(AT_ERR_ARG, "workspace NULL or not 256-byte aligned");
@@ -1353,8 +1382,10 @@ at_status at_batch_init(const at_config *cfgs, int32_t count, void *workspace,
     b->cfg.assign(cfgs, cfgs + count);
     b->d = ds;
     b->R = Rs;
-    b->max_fuse = smax;
-    b->fuse = cfgs[0].fuse_steps > 0 ? std::min<int>(cfgs[0].fuse_steps, smax) : 1;
+    for (int i = 0; i < 3; ++i) b->mf_ppt[i] = mfp[i];
+    b->ppt = 16;
+    b->max_fuse = mfp[0];
+    b->fuse = cfgs[0].fuse_steps > 0 ? std::min<int>(cfgs[0].fuse_steps, b->max_fuse) : 1;
     b->nsteps_max = cfgs[0].nsteps_max;
     b->tbl_cap = cap;
     for (int s = 0; s < 2; ++s) {
@@ -1403,6 +1434,20 @@ at_status at_batch_set_fuse(at_batch *b, int32_t s)
     return AT_OK;
 }
 
+at_status at_batch_set_variant(at_batch *b, int32_t v)
+{
+    if (!b) return fail(AT_ERR_ARG, "null batch");
+    if (v < 0 || v > 3) return fail(AT_ERR_ARG, "batch variant must be in 0..3");
+    const int idx = v <= 1 ? 0 : v - 1;               // 16, 8, 4 points per thread
+    b->variant = v;
+    b->ppt = idx == 0 ? 16 : (idx == 1 ? 8 : 4);
+    b->max_fuse = b->mf_ppt[idx];
+    b->fuse = std::min(b->fuse, b->max_fuse);
+    b->slot_s[0] = b->slot_s[1] = 0;                  // tables are rebuilt for the new layout
+    drop_graph(b);
+    return AT_OK;
+}
+
 at_status at_batch_reset(at_batch *b)
 {
     if (!b) return fail(AT_ERR_ARG, "null batch");
@@ -1425,7 +1470,7 @@ at_status at_batch_run(at_batch *b, double *const *u, double *const *scr, int64_
     if (nsteps == 0) return AT_OK;
     const uint64_t key = ptr_key(u, scr, b->count);
     if (use_graph && b->has_graph && b->g_n0 == b->n && b->g_nsteps == nsteps &&
-        b->g_fuse == b->fuse && b->g_key == key) {
+        b->g_fuse == b->fuse && b->g_ppt == b->ppt && b->g_key == key) {
         AT_HIP(hipGraphLaunch(b->gexec, b->st));
         b->n += nsteps;
         return AT_OK;
@@ -1461,6 +1506,7 @@ at_status at_batch_run(at_batch *b, double *const *u, double *const *scr, int64_
     b->g_n0 = b->n;
     b->g_nsteps = nsteps;
     b->g_fuse = b->fuse;
+    b->g_ppt = b->ppt;
     b->g_key = key;
     AT_HIP(hipGraphLaunch(b->gexec, b->st));
     b->n += nsteps;
@@ -1477,44 +1523,63 @@ at_status at_batch_autotune(at_batch *b, double *const *u0, double *const *t1,
     static const int cands[] = {1, 2, 3, 4, 6, 8, 10, 12, 16, 20, 24, 32, 40, 48, 56, 64};
     hipEvent_t e0, e1;
     AT_HIP(hipEventCreate(&e0));
-    AT_HIP(hipEventCreate(&e1));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(AT_ERR_HIP, "at_batch_autotune: hipEventCreate failed");
+    }
+    // points per thread (variants 1, 2, 3: 16, 8, 4) and steps per launch
     float best_ms = 1e30f;
-    int best = 1;
-    for (int s : cands) {
-        if (s > b->max_fuse) break;
-        float ms_best = 1e30f;
-        for (int rep = 0; rep < 2; ++rep) {
-            at_status st = at_batch_reset(b);
-            if (st) return st;
-            for (int j = 0; j < b->count; ++j) AT_HIP(launch_copy(t1[j], u0[j], b->d[j].N, b->st));
-            b->fuse = s;
-            AT_HIP(hipEventRecord(e0, b->st));
-            st = at_batch_run(b, t1, t2, trial_steps, 0);
-            if (st) { b->n = 0; return st; }
-            AT_HIP(hipEventRecord(e1, b->st));
-            AT_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            AT_HIP(hipEventElapsedTime(&ms, e0, e1));
-            ms_best = std::min(ms_best, ms);
+    int best_s = 1, best_v = 1;
+    at_status st = AT_OK;
+    for (int v = 1; v <= 3 && st == AT_OK; ++v) {
+        st = at_batch_set_variant(b, v);
+        for (int s : cands) {
+            if (st != AT_OK || s > b->max_fuse) break;
+            float ms_best = 1e30f;
+            for (int rep = 0; rep < 2 && st == AT_OK; ++rep) {
+                st = at_batch_reset(b);
+                hipError_t e = hipSuccess;
+                for (int j = 0; j < b->count && st == AT_OK && e == hipSuccess; ++j)
+                    e = launch_copy(t1[j], u0[j], b->d[j].N, b->st);
+                b->fuse = s;
+                if (st == AT_OK && e == hipSuccess) e = hipEventRecord(e0, b->st);
+                if (st == AT_OK && e == hipSuccess) st = at_batch_run(b, t1, t2, trial_steps, 0);
+                if (st == AT_OK && e == hipSuccess) e = hipEventRecord(e1, b->st);
+                if (st == AT_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (st == AT_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess && st == AT_OK)
+                    st = fail(AT_ERR_HIP, "at_batch_autotune: %s", hipGetErrorString(e));
+                ms_best = std::min(ms_best, ms);
+            }
+            if (st == AT_OK && ms_best < best_ms * 0.98f) {
+                best_ms = ms_best;
+                best_s = s;
+                best_v = v;
+            }
         }
-        if (ms_best < best_ms * 0.98f) { best_ms = ms_best; best = s; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    at_status st = at_batch_reset(b);
+    if (st) { b->n = 0; return st; }
+    st = at_batch_set_variant(b, best_v);
+    if (st) return st;
+    st = at_batch_reset(b);
     if (st) return st;
     AT_HIP(hipStreamSynchronize(b->st));
-    b->fuse = best;
-    if (chosen) *chosen = best;
+    b->fuse = best_s;
+    if (chosen) *chosen = best_s;
     return AT_OK;
 }
 
-at_status at_batch_query(const at_batch *b, int64_t *n, int32_t *fuse, int32_t *max_fuse)
+at_status at_batch_query(const at_batch *b, int64_t *n, int32_t *fuse, int32_t *max_fuse,
+                         int32_t *variant)
 {
     if (!b) return fail(AT_ERR_ARG, "null batch");
     if (n) *n = b->n;
     if (fuse) *fuse = b->fuse;
     if (max_fuse) *max_fuse = b->max_fuse;
+    if (variant) *variant = b->variant;
     return AT_OK;
 }
 

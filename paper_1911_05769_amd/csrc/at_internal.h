@@ -123,7 +123,7 @@ int step1d_plain_points_per_thread();
 hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, bool fma, int ppt,
                          int64_t nblocks, hipStream_t st);
 hipError_t launch_step1d_batch(const Step1D *descs, const int2 *tbl, int64_t nblocks, int order,
-                               bool linear, bool fma, int64_t n0, int flip, size_t lds,
+                               bool linear, bool fma, int ppt, int64_t n0, int flip, size_t lds,
                                hipStream_t st);
 hipError_t launch_adj1d(const Adj1D &a, int order, bool linear, int64_t nblocks,
                         hipStream_t st);

@@ -500,7 +500,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d_plain(Step1D a)
 // Batched form: workgroup b advances chunk tbl[b].y of instance tbl[b].x;
 // instance descriptors carry each instance's grid, ring, delays and
 // coefficients; flip = 1 swaps the field pointers (ping-pong launches).
-template <int ORDER, bool LINEAR, bool FMA>
+template <int ORDER, bool LINEAR, bool FMA, int PPT>
 __global__ __launch_bounds__(kThreads) void k_step1d_aligned_batch(const Step1D *descs,
                                                                    const int2 *tbl, int64_t n0,
                                                                    int flip)
@@ -514,7 +514,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d_aligned_batch(const Step1D 
         a.uin = a.uout;
         a.uout = const_cast<double *>(t);
     }
-    step1d_aligned_body<ORDER, LINEAR, FMA, true, kPPT, true>(a, e.y);
+    step1d_aligned_body<ORDER, LINEAR, FMA, true, PPT, true>(a, e.y);
 }
 
 }  // namespace
@@ -579,18 +579,25 @@ hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, 
 }
 
 hipError_t launch_step1d_batch(const Step1D *descs, const int2 *tbl, int64_t nblocks, int order,
-                               bool linear, bool fma, int64_t n0, int flip, size_t lds,
+                               bool linear, bool fma, int ppt, int64_t n0, int flip, size_t lds,
                                hipStream_t st)
 {
     dim3 grid((unsigned)nblocks), block(kThreads);
-#define AT_BATCH(O, LI, F) hipLaunchKernelGGL((k_step1d_aligned_batch<O, LI, F>), grid, block, lds, st, descs, tbl, n0, flip)
+#define AT_BATCH(O, LI, F, P) hipLaunchKernelGGL((k_step1d_aligned_batch<O, LI, F, P>), grid, block, lds, st, descs, tbl, n0, flip)
+#define AT_BATCH_P(O, LI, F)                                                             \
+    do {                                                                                 \
+        if (ppt == 16) AT_BATCH(O, LI, F, 16);                                           \
+        else if (ppt == 8) AT_BATCH(O, LI, F, 8);                                        \
+        else AT_BATCH(O, LI, F, 4);                                                      \
+    } while (0)
     if (order == 2) {
-        if (linear) { if (fma) AT_BATCH(2, true, true); else AT_BATCH(2, true, false); }
-        else { if (fma) AT_BATCH(2, false, true); else AT_BATCH(2, false, false); }
+        if (linear) { if (fma) AT_BATCH_P(2, true, true); else AT_BATCH_P(2, true, false); }
+        else { if (fma) AT_BATCH_P(2, false, true); else AT_BATCH_P(2, false, false); }
     } else {
-        if (linear) { if (fma) AT_BATCH(4, true, true); else AT_BATCH(4, true, false); }
-        else { if (fma) AT_BATCH(4, false, true); else AT_BATCH(4, false, false); }
+        if (linear) { if (fma) AT_BATCH_P(4, true, true); else AT_BATCH_P(4, true, false); }
+        else { if (fma) AT_BATCH_P(4, false, true); else AT_BATCH_P(4, false, false); }
     }
+#undef AT_BATCH_P
 #undef AT_BATCH
     return hipGetLastError();
 }

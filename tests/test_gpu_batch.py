@@ -127,3 +127,51 @@ def test_batch_full_workload_sampled(gpu):
         assert np.max(np.abs(got - o)) <= 1e-12 * np.max(np.abs(o))
     for u in us:
         assert bool(torch.isfinite(u).all())
+
+
+def test_batch_points_per_thread_variants_and_autotune(gpu):
+    """Every points-per-thread variant of the batched kernel (16, 8, 4) at
+    several steps per launch gives each instance's standalone bits; the
+    autotuner picks a (variant, steps per launch) pair and keeps the bits."""
+    wls = small_instances(nsteps=90)
+    nst = wls[0].nsteps
+    refs = [standalone(gpu, w, nst)[0] for w in wls]
+    b = gpu.Batch.from_workloads(wls)
+    for v in (1, 2, 3):
+        b.set_variant(v)
+        assert b.variant == v
+        mf = b.query()[2]
+        for s in sorted({1, 3, min(8, mf), mf}):
+            b.reset()
+            us = [dev(w.u0) for w in wls]
+            ss = [torch.empty_like(u) for u in us]
+            b.set_fuse(s)
+            b.run(us, ss, nst, use_graph=(s == mf))
+            torch.cuda.synchronize()
+            for j, (u, r) in enumerate(zip(us, refs)):
+                assert torch.equal(u, r), "variant %d, s %d, instance %d" % (v, s, j)
+        log("  batch variant %d: steps per launch up to %d, bits equal" % (v, mf))
+    b.reset()
+    u0 = [dev(w.u0) for w in wls]
+    s = b.autotune(u0, 30)
+    log("  batch autotune: variant %d, steps per launch %d" % (b.variant, s))
+    assert b.variant in (1, 2, 3) and 1 <= s <= b.query()[2]
+    us = [u.clone() for u in u0]
+    b.run(us, [torch.empty_like(u) for u in us], nst)
+    torch.cuda.synchronize()
+    assert all(torch.equal(u, r) for u, r in zip(us, refs))
+
+
+def test_standalone_autotune_picks_points_per_thread(gpu):
+    """The 1D autotuner searches points per thread (variants 1-3) together
+    with steps per launch; the chosen pair gives the one-step bits."""
+    w = small_instances(nsteps=200)[5]             # 8192 points, 32 tiles of 256
+    ref, _ = standalone(gpu, w, 200)
+    st = gpu.Stepper(n=w.n[0], p=w.p[0], order=w.order, L=w.L, nu=w.nu, dt=w.dt,
+                     nsteps_max=w.nsteps, seed=w.seed, dist=w.dist)
+    s = st.autotune(dev(w.u0), 60)
+    log("  autotune: variant %d, steps per launch %d" % (st.variant, s))
+    assert st.variant in (1, 2, 3) and st.query()[1] == s
+    u = dev(w.u0)
+    st.run(u, torch.empty_like(u), 200)
+    assert torch.equal(u, ref)
