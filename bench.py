@@ -150,6 +150,7 @@ def bench_c2(args, torch, at, I, fuse=None, label="main", arith=0):
     eprint("[%s] fuse %d, %d points/thread: %.3f ms/run, %.4g updates/s, kernel %.1f us/launch, "
            "%.0f GB/s, %.2f TFLOP/s" % (label, s, ppt, res["ms_per_step"], res["value"],
                                         ms_launch * 1e3, gbps, tflops))
+    st.close()
     return res
 
 
@@ -274,6 +275,7 @@ def copy_ceiling_lib(torch, at, n=1 << 27, reps=5):
         st.restore(snap, u)
         tm.stop()
     ms = tm.total_ms() / reps
+    st.close()
     del st, u, snap
     return ms, 16.0 * n / (ms * 1e-3) / 1e9
 
@@ -429,6 +431,8 @@ def bench_batched(args, torch, at, I):
     per_instance()
     w1, k1 = _timed(torch, per_instance)
     ref = [u.clone() for u in us]
+    for st in steppers:
+        st.close()
     del steppers, snaps
     # (ii) batched, one launch per step, no graph; (iii) fused + graph
     b = at.Batch.from_workloads(wls)
@@ -475,6 +479,7 @@ def bench_batched(args, torch, at, I):
     eprint("[batched] %d instances, %d points: per-instance %.1f ms, one launch/step %.1f ms, "
            "fused(s=%d, variant %d)+graph %.2f ms (%.3g updates/s)" %
            (len(wls), pts, k1 * 1e3, k2 * 1e3, s, b.variant, k3 * 1e3, upd / k3))
+    b.close()
     return res
 
 
@@ -505,6 +510,8 @@ def bench_adjoint(args, torch, at, I):
         ev[2].record()
         torch.cuda.synchronize()
         times.append((ev[0].elapsed_time(ev[1]) * 1e-3, ev[1].elapsed_time(ev[2]) * 1e-3))
+        st.close()
+    tst.close()
     tf = min(t[0] for t in times)
     ta = min(t[1] for t in times)
     pstep = N * nst
@@ -615,6 +622,7 @@ def bench_ws(args, torch, at, I):
                     best = ms
                     hist = np.bincount(st.delays()[:nst].ravel().astype(np.int64),
                                        minlength=L + 1)
+                st.close()
             frac = (hist / hist.sum()).round(4).tolist()
             eprint("[ws] jitter %d, L=%d: %.2f ms/run (%.2f us/step), delays k=0..%d: %s" %
                    (jitter, L, best, best * 1e3 / nst, L, frac))
@@ -638,6 +646,7 @@ def bench_ws(args, torch, at, I):
     eprint("[ws] prescribed delays, fused s=%d: %.2f ms/run" % (fuse, ms))
     out["prescribed_L3"] = {"ms_per_run": round(ms, 3), "fuse_steps": fuse,
                             "updates_per_s": N * nst / (ms * 1e-3)}
+    st.close()
     # 3D: 512^3 x 3, 8^3 blocks of 64^3, one resident workgroup per block
     w3 = I.wl_solenoidal_3d()
     nst3 = w3.nsteps
@@ -658,7 +667,7 @@ def bench_ws(args, torch, at, I):
             if rep > 0 and (best is None or ms < best):
                 best = ms
                 hist = np.bincount(st.delays()[:nst3].ravel().astype(np.int64), minlength=L + 1)
-            del st
+            st.close()
         frac = (hist / hist.sum()).round(4).tolist()
         eprint("[ws] 3D L=%d: %.1f ms/run (%.3f ms/step), delays k=0..%d: %s" %
                (L, best, best / nst3, L, frac))
@@ -679,6 +688,7 @@ def bench_ws(args, torch, at, I):
     ms = tm.total_ms()
     eprint("[ws] 3D prescribed delays, variant %d: %.1f ms/run" % (var, ms))
     out["prescribed3d_L3"] = {"ms_per_run": round(ms, 3), "kernel_variant": var}
+    st.close()
     out["value"] = out["ws_L3_jitter0"]["updates_per_s"]
     out["unit"] = "grid-point updates/s (weakly-synchronous, emergent delays)"
     return out
@@ -714,6 +724,7 @@ def _bench_3d_run(args, torch, at, wl, alpha, tag):
     ring_b = face_frac * 8.0 * nc * (1 + 2 * wl.L / (wl.L + 1.0))
     bpu = 16.0 * nc + ring_b
     gbps = npt * wl.nsteps * bpu / sec / 1e9
+    st.close()
     eprint("[%s] variant %d" % (tag, var))
     eprint("[%s] %s: %.2f ms/run, %.3g point-updates/s, %.0f GB/s (%.1f B/update)" %
            (tag, wl.name, sec * 1e3, npt * wl.nsteps / sec, gbps, bpu))
