@@ -36,7 +36,10 @@ METRIC = "grid-point updates/s & % HBM peak (AT step, adjoint, batched) vs plain
 # (bytes_per_launch None) until they have been taken on the current source.
 TRAFFIC = {"sources": ["paper_1911_05769_amd/csrc/at_step1d.hip",
                        "paper_1911_05769_amd/csrc/at_stencil1d.h"],
-           "md5": None, "fuse": 56, "bytes_per_launch": None}
+           "md5": "f8c70516af3b5c5db96cae5e7f53c07a", "fuse": 56,
+           # FETCH_SIZE 73266.9 KiB x 2.0 + WRITE_SIZE 145408.0 KiB x 1.0, mean of the 35
+           # 56-step launches of one 2000-step run
+           "bytes_per_launch": 298948403.2}
 
 
 def eprint(*a):
@@ -141,7 +144,8 @@ def bench_c2(args, torch, at, I, fuse=None, label="main", arith=0):
     # issue-rate ceiling for this instruction mix: 39.3 T FP64 instructions/s
     # (a diagnostic; the roofline's peak is the published 78.6 TFLOP/s)
     issue_ceiling = FP64_ISSUE_TINSTR * fl / ins
-    ppt = {1: 16, 2: 8, 3: 4}.get(st.variant, 16)
+    # one step per launch runs the plain kernel (8 points per thread)
+    ppt = 8 if s == 1 else {1: 16, 2: 8, 3: 4}.get(st.variant, 16)
     res = dict(wl=wl, s=s, ppt=ppt, wall=wall, ms_per_step=wall * 1e3 / args.steps, run_ms=run_ms,
                value=N * wl.nsteps * args.steps / wall, ms_launch=ms_launch, gbps=gbps,
                tflops=tflops, issue_ceiling=issue_ceiling, arith=arith, launches=launches,
