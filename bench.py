@@ -47,14 +47,15 @@ def eprint(*a):
 
 
 def flops_per_update(order, arith=0):
-    """(FP64 flops, FP64 VALU instructions) of one interior update.  Exact
-    order: order 2 has 11 flops, order 4 17; the exact scalings by 2, 8 and 16
-    share an fma with the next add (one rounding either way), so they take
-    10 and 15 instructions.  Contracted mode (an FMA is two flops in one
-    instruction): order 2: 9 flops in 6 instructions, order 4: 15 in 10."""
+    """(flops, FP64 VALU instructions) of one interior update.  The flops are
+    the method's own (section 3.2's central differences and the Euler update):
+    11 for order 2, 17 for order 4, in every arithmetic mode.  Instructions:
+    exact order issues order 2 in 10 and order 4 in 15 (the exact scalings by
+    2, 8 and 16 share an fma with the next add, one rounding either way); the
+    contracted mode issues order 2 in 6 and order 4 in 10."""
     if arith == 0:
         return (11, 10) if order == 2 else (17, 15)
-    return (9, 6) if order == 2 else (15, 10)
+    return (11, 6) if order == 2 else (17, 10)
 
 
 def algo_bytes_1d(N, P, order, L, dist, s):
