@@ -36,10 +36,10 @@ METRIC = "grid-point updates/s & % HBM peak (AT step, adjoint, batched) vs plain
 # (bytes_per_launch None) until they have been taken on the current source.
 TRAFFIC = {"sources": ["paper_1911_05769_amd/csrc/at_step1d.hip",
                        "paper_1911_05769_amd/csrc/at_stencil1d.h"],
-           "md5": "f8c70516af3b5c5db96cae5e7f53c07a", "fuse": 56,
-           # FETCH_SIZE 73266.9 KiB x 2.0 + WRITE_SIZE 145408.0 KiB x 1.0, mean of the 35
+           "md5": "86582eab1c5c59a7d6543176244107c3", "fuse": 56,
+           # FETCH_SIZE 73255.0 KiB x 2.0 + WRITE_SIZE 132608.0 KiB x 1.0, mean of the 35
            # 56-step launches of one 2000-step run
-           "bytes_per_launch": 298948403.2}
+           "bytes_per_launch": 285816832.0}
 
 
 def eprint(*a):
@@ -60,13 +60,22 @@ def flops_per_update(order, arith=0):
 
 def algo_bytes_1d(N, P, order, L, dist, s):
     """Algorithmic HBM bytes of one launch advancing s steps: the field in and
-    out once, plus per step the ring publish (2P*h doubles), the expected
-    delayed-edge reads (m levels for faces with k > 0) and the delay row."""
+    out once, the delay rows (2P bytes per step), and the ring traffic.  One
+    step per launch reads the delayed edge levels it uses from the ring (m
+    levels of the faces with k > 0) and publishes its level; a fused launch
+    copies the D = L + m - 1 edge levels below its first step into LDS once,
+    takes every later delayed level from there, and publishes only its last
+    min(s, D) levels (the ones the next launch reads)."""
     h = order // 2
     m = 2 if order == 2 else 3
-    pk = (L / (L + 1.0)) if dist == 0 else (0.5 if L > 0 else 0.0)
-    per_step = 2 * P * h * 8 + 2 * P * h * 8 * m * pk + 2 * P
-    return 16.0 * N + s * per_step
+    D = L + m - 1
+    edge_level = 2 * P * h * 8                       # one level of every tile edge
+    if s == 1:
+        pk = (L / (L + 1.0)) if dist == 0 else (0.5 if L > 0 else 0.0)
+        ring = edge_level + edge_level * m * pk
+    else:
+        ring = edge_level * D + edge_level * min(s, D)
+    return 16.0 * N + ring + s * 2 * P
 
 
 class Timer:

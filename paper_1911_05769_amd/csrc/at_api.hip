@@ -701,7 +701,10 @@ at_status run_launches(at_ctx *c, double *u, double *scratch, int64_t nsteps)
                 AT_HIP(launch_copy(c->ckpt + (c->n / C) * c->d.N, cur, c->d.N, c->st));
             s = std::min<int64_t>(s, C - c->n % C);
         }
-        at_status st = launch_any(c, cur, oth, c->n, (int)s, 1);
+        // 1D without the edge tape: only the last L + m - 1 levels of a launch
+        // reach the ring (the next launch reads no older level)
+        at_status st = launch_any(c, cur, oth, c->n, (int)s,
+                                  (c->d.dim == 1 && !c->cfg.record) ? 2 : 1);
         if (st) return st;
         std::swap(cur, oth);
         c->n += s;
@@ -1208,7 +1211,7 @@ at_status batch_tables(at_batch *b, int slot, int s, double *const *u, double *c
         a.R = b->R[j];
         a.NT = (int)((reg - 1) / d.W + 2);
         a.stale = b->cfg[j].halo_mode;
-        a.publish = 1;
+        a.publish = 2;        // no edge tape: the last D levels of a launch
         a.RL = (int32_t)rg.RL;
         a.slot0 = 0;          // set per launch by the batched kernel
         a.D = b->cfg[j].L + d.m - 1;

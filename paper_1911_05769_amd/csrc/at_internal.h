@@ -24,7 +24,8 @@ struct Step1D {
     int32_t R;                // ring levels
     int32_t NT;               // region-local tile slots in the LDS edge history
     int32_t stale;            // 1: halo = level n-k without extrapolation
-    int32_t publish;          // 1: write level n edges to the ring
+    int32_t publish;          // ring writes of level edges: 0 none, 1 every level,
+                              // 2 the last D levels of the launch (1D)
     int32_t RL;               // left rim of the loaded region (aligned kernel)
     int32_t slot0;            // n0 mod R (ring slot of level n0)
     int32_t D;                // delayed levels below n0 a step may read: L + m - 1

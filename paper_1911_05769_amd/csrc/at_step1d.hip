@@ -28,7 +28,9 @@
 //     one launch per step;
 //   * edge values of in-launch levels are kept in an LDS edge history for
 //     delayed halo reads; levels before n0 come from the ring in HBM;
-//   * every owned tile-edge point of level n is published to ring slot n mod R.
+//   * owned tile-edge points are published to ring slot n mod R: those of every
+//     level when the run keeps the edge tape for the adjoint, else those of the
+//     last L + m - 1 levels of a launch, the only ones a later launch reads.
 #include "at_internal.h"
 #include "at_stencil1d.h"
 
@@ -53,6 +55,14 @@ __device__ __forceinline__ int64_t ring_slot(const Step1D &a, int64_t d)
     if (x < 0) x += a.R;
     if (x >= a.R) x -= a.R;
     return x;
+}
+
+// whether step t of a launch of S steps writes its level's tile edges to the
+// ring: every level (publish 1), or only the last D levels of the launch
+// (publish 2), the only ones a later launch reads when no edge tape is kept
+__device__ __forceinline__ bool publish_level(const Step1D &a, int t, int S)
+{
+    return a.publish == 1 || (a.publish == 2 && t + a.D >= S);
 }
 
 // Level n0 of a region of E points that starts at periodic index G0w (in
@@ -130,6 +140,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
         // ---- edge points of level n: LDS history for later steps, ring for later launches
         if (has_edge) {
             const int64_t slot = ring_slot(a, t);
+            const bool pub = publish_level(a, t, a.s);
 #pragma unroll
             for (int j = 0; j < PPT; ++j) {
                 const int rp = rp0 + j;
@@ -142,7 +153,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
                     const int q = lo ? (int)oj : (int)(oj - (a.W - H));
                     if (t < a.s - 1)
                         eh[((t * a.NT + (tl0 + e)) * 2 + side) * H + q] = w[H + j];
-                    if (a.publish && rp >= sh && rp < sh + owned) {
+                    if (pub && rp >= sh && rp < sh + owned) {
                         int64_t tp = tp0 + e;
                         while (tp >= a.P) tp -= a.P;
                         a.ring[((slot * a.P + tp) * 2 + side) * H + q] = w[H + j];
@@ -355,15 +366,16 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
         const int64_t slot = ring_slot(a, t);
         // ---- record this level's tile edges (LDS history; ring when owned)
         if (lo_edge || hi_edge) {
+            const bool pub = publish_level(a, t, S);
 #pragma unroll
             for (int q = 0; q < H; ++q) {
                 if (lo_edge) {
                     if (FUSED && t < S - 1) eh[(((t + D) * a.NT + tl0) * 2 + 0) * H + q] = w[H + q];
-                    if (a.publish && owns) a.ring[((slot * a.P + tp0) * 2 + 0) * H + q] = w[H + q];
+                    if (pub && owns) a.ring[((slot * a.P + tp0) * 2 + 0) * H + q] = w[H + q];
                 }
                 if (hi_edge) {
                     if (FUSED && t < S - 1) eh[(((t + D) * a.NT + tl0) * 2 + 1) * H + q] = w[PPT + q];
-                    if (a.publish && owns) a.ring[((slot * a.P + tp0) * 2 + 1) * H + q] = w[PPT + q];
+                    if (pub && owns) a.ring[((slot * a.P + tp0) * 2 + 1) * H + q] = w[PPT + q];
                 }
             }
         }
