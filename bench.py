@@ -316,6 +316,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fuse", type=int, default=None,
                     help="steps per launch of the headline run (default: autotuned)")
+    ap.add_argument("--variant3d", type=int, default=None,
+                    help="3D legs: run this kernel variant instead of the autotuned one")
     ap.add_argument("--calibrate", action="store_true",
                     help="only copy 1 GiB of doubles 5 times (counter scale reference)")
     args = ap.parse_args()
@@ -718,7 +720,11 @@ def _bench_3d_run(args, torch, at, wl, alpha, tag):
     st = at.Stepper(dim=3, n=wl.n, p=wl.p, order=2, L=wl.L, nu=wl.nu, dt=wl.dt,
                     nsteps_max=wl.nsteps, seed=wl.seed, dist=wl.dist, alpha=alpha)
     u0 = torch.from_numpy(wl.u0).cuda()
-    var = st.autotune(u0, 6)
+    if args.variant3d is None:
+        var = st.autotune(u0, 6)
+    else:
+        st.set_variant(args.variant3d)
+        var = args.variant3d
     snap = st.snapshot(u0)
     u = torch.empty_like(u0)
     s = torch.empty_like(u0)

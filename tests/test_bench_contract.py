@@ -53,3 +53,19 @@ def test_roofline_uses_published_peaks():
     assert dom["bound"] == "alu" and dom["peak"] == 78.6
     assert abs(dom["frac"] - 29.4 / 78.6) < 1e-4
     assert other["bound"] == "hbm" and other["peak"] == 8000.0
+
+
+def test_algorithmic_bytes_model():
+    """One step per launch: field in and out, the level's edges published, the
+    delayed edge levels read for the faces with k > 0, the delay row.  A
+    fused launch: field once, D = L + m - 1 edge levels read into LDS and the
+    last min(s, D) published, s delay rows."""
+    b = _bench_module()
+    N, P, L = 1 << 24, 4096, 4
+    edge = 2 * P * 2 * 8                                   # order 4: h = 2
+    plain = b.algo_bytes_1d(N, P, 4, L, 1, 1)
+    assert plain == 16.0 * N + edge + edge * 3 * 0.5 + 2 * P
+    fused = b.algo_bytes_1d(N, P, 4, L, 1, 56)
+    assert fused == 16.0 * N + edge * 6 + edge * 6 + 56 * 2 * P
+    assert b.algo_bytes_1d(N, P, 4, L, 1, 3) == 16.0 * N + edge * 6 + edge * 3 + 3 * 2 * P
+    assert b.algo_bytes_1d(1024, 8, 2, 2, 0, 1) == 16.0 * 1024 + 16 * 8 + 16 * 8 * 2 * (2 / 3) + 16
