@@ -491,6 +491,9 @@ def bench_batched(args, torch, at, I):
         "speedup_vs_per_instance": round(k1 / k3, 2),
         "speedup_vs_one_launch_per_step": round(k2 / k3, 2),
         "one_launch_per_step_hbm_gbps": round(algo / k2 / 1e9, 1),
+        # the method's 17 flops per order-4 update against the published FP64 peak
+        "fp64_tflops": round(17.0 * upd / k3 / 1e12, 3),
+        "fp64_frac": round(17.0 * upd / k3 / 1e12 / FP64_PEAK_TFLOPS, 4),
         "bitwise_equal_to_per_instance": bool(same)})
     eprint("[batched] %d instances, %d points: per-instance %.1f ms, one launch/step %.1f ms, "
            "fused(s=%d, variant %d)+graph %.2f ms (%.3g updates/s)" %
