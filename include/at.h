@@ -148,8 +148,11 @@ at_status at_step(at_ctx *ctx, const double *u_in, double *u_out);
 /* Advance nsteps steps from the current level held in u; the result is left
  * in u.  scratch is a second field of the same size.  Steps are fused s at a
  * time (fuse_steps or the autotuned value); results are bit-identical for
- * every s.  Record mode also stores a checkpoint of u every ckpt_every
- * steps, counted from n = 0. */
+ * every s.  A 1D launch of s steps writes to the ring the tile edges of its
+ * last L + m - 1 levels (the levels a later step reads; earlier ones stay in
+ * the launch's LDS history), or of every level in record mode, where the ring
+ * is the adjoint's edge tape.  Record mode also stores a checkpoint of u
+ * every ckpt_every steps, counted from n = 0. */
 at_status at_run(at_ctx *ctx, double *u, double *scratch, int64_t nsteps);
 
 /* Weakly-synchronous run with EMERGENT delays (paper section 5.2, Algorithm 2;
