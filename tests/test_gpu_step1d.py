@@ -84,6 +84,7 @@ CASES = [
     ("narrow_tiles_n600_p300_o2", 600, 300, 2, 3, 0, 0.02, 150, {}),
     ("stale_n2048_p16_o2", 2048, 16, 2, 3, 0, 0.02, 300, {"halo_mode": 1}),
     ("linear_n2048_p8_o4", 2048, 8, 4, 2, 0, 0.02, 300, {"adv_mode": 1, "adv_speed": 0.8}),
+    ("max_delay_n2048_p16_o2_L15", 2048, 16, 2, 15, 1, 0.02, 150, {}),
 ]
 
 
@@ -130,6 +131,7 @@ FUSE_CASES = [
     ("w2_n1000_p500_o2", 1000, 500, 2, 2, 0, 0.02, 40),
     ("w4_n4000_p1000_o4", 4000, 1000, 4, 2, 1, 0.02, 40),
     ("ragged_n12345_p5_o4", 12345, 5, 4, 3, 0, 0.01, 77),
+    ("max_delay_n8192_p8_o4_L15", 8192, 8, 4, 15, 1, 0.01, 90),
 ]
 
 

@@ -43,6 +43,7 @@ CASES = [
     ("n96x48x40_p4x3x2_L3", (96, 48, 40), (4, 3, 2), 3, 0, 0.01, 30, False),
     ("n130x18x6_p65x9x3_w2", (130, 18, 6), (65, 9, 3), 2, 0, 0.02, 25, False),
     ("n32_p4_stale", (32, 32, 32), (4, 4, 4), 3, 0, 0.02, 30, True),
+    ("n32_p2_L7", (32, 32, 32), (2, 2, 2), 7, 1, 0.02, 40, False),
 ]
 
 
