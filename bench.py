@@ -550,18 +550,23 @@ def bench_c1(args, torch, at, I):
     """The small correctness configuration: N = 1024, P = 8, order 2, L = 2,
     1000 steps (8 KB of state: launch-latency bound).  Microseconds per step
     for one launch per step and for the autotuned steps per launch, each with
-    launches issued one by one and replayed from a captured HIP graph."""
+    launches issued one by one and replayed from a captured HIP graph, and for
+    the whole grid in one workgroup (one launch per run)."""
     wl = I.wl_sines_1d()
     N, P = wl.n[0], wl.p[0]
     u0 = torch.from_numpy(wl.u0).cuda()
     out = {"workload": wl.name}
     uT = {}
     for label, fuse, graph in (("plain", 1, False), ("plain_graph", 1, True),
-                               ("fused", 0, False), ("fused_graph", 0, True)):
+                               ("fused", 0, False), ("fused_graph", 0, True),
+                               ("single_workgroup", -1, False)):
         st = at.Stepper(n=N, p=P, order=2, L=wl.L, nu=wl.nu, dt=wl.dt, nsteps_max=wl.nsteps,
                         seed=wl.seed, dist=wl.dist)
         if fuse == 0:
             fuse = st.autotune(u0, 100)
+        elif fuse < 0:
+            st.set_variant(4)                 # the whole grid in one workgroup
+            fuse = st.query()[1]
         else:
             st.set_fuse(fuse)
         st.set_graph(graph)
@@ -583,7 +588,8 @@ def bench_c1(args, torch, at, I):
                       "graph_replay": graph}
         st.close()
     out["bitwise_equal"] = all(bool(torch.equal(uT["plain"], uT[x]))
-                               for x in ("plain_graph", "fused", "fused_graph"))
+                               for x in ("plain_graph", "fused", "fused_graph",
+                                         "single_workgroup"))
     # the weakly-synchronous run: 8 one-wave workgroups, emergent delays
     import numpy as np
     ws_ms, hist = [], None
@@ -607,7 +613,7 @@ def bench_c1(args, torch, at, I):
     out["weakly_synchronous"] = {"us_per_step": round(us, 3), "timing": sp,
                                  "delay_fractions": frac}
     out["value"] = min(out[x]["us_per_step"] for x in ("plain", "plain_graph", "fused",
-                                                       "fused_graph"))
+                                                       "fused_graph", "single_workgroup"))
     out["unit"] = "us/step (lower is better)"
     return out
 

@@ -212,13 +212,14 @@ at_status at_set_graph(at_ctx *ctx, int32_t use_graph);
 at_status at_set_debug(at_ctx *ctx, int32_t flags);
 
 /* Choose the launch shape -- 1D: points per thread (the variant, 16, 8 or 4
- * among those dividing the tile width) together with steps per launch s; 3D:
+ * among those dividing the tile width) together with steps per launch s, and
+ * the whole-grid variant 4 where the grid fits one workgroup; 3D:
  * the kernel variant (including the two-step variants) -- nothing that
  * changes results -- by timing `trial_steps` steps from u0 for each
  * candidate; requires n == 0 and leaves the context at n = 0 with the ring
  * cleared.  u0 is not modified; t1 and t2 are two scratch fields.
- * Synchronises the stream.  *chosen receives s (1D) or the variant (3D);
- * at_query returns both. */
+ * Synchronises the stream.  *chosen receives s (1D; nsteps_max for variant
+ * 4) or the variant (3D); at_query returns both. */
 at_status at_autotune(at_ctx *ctx, const double *u0, double *t1, double *t2,
                       int32_t trial_steps, int32_t *chosen);
 
@@ -236,7 +237,13 @@ at_status at_autotune(at_ctx *ctx, const double *u0, double *t1, double *t2,
  * and at_step use a one-step variant); choosing another sets it to 1, and
  * at_set_fuse(ctx, 2) selects 15 (or 16).  1D contexts: 0 automatic; 1, 2, 3 for 16, 8
  * and 4 points per thread in the fused launches (the tile width must be
- * divisible by it, AT_ERR_ARG otherwise); every choice gives the same bits. */
+ * divisible by it, AT_ERR_ARG otherwise); 4 for the whole periodic grid in
+ * one workgroup of 256 threads (N <= 256 x 16, with N and the tile width
+ * multiples of the 4, 8 or 16 points a thread holds, AT_ERR_ARG otherwise):
+ * no rim is recomputed, the neighbour exchange wraps around the workgroup,
+ * and one launch advances a whole at_run call (choosing it sets the steps
+ * per launch to nsteps_max; at_set_fuse can lower it); every choice gives the
+ * same bits. */
 at_status at_set_variant(at_ctx *ctx, int32_t variant);
 
 /* Current step n, steps per launch in use, ring levels R, kernel variant

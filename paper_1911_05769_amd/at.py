@@ -327,6 +327,9 @@ class Stepper:
         _check(lib().at_set_adjoint_fuse(self._ctx, int(s)), "at_set_adjoint_fuse")
 
     def set_variant(self, v: int):
+        """Kernel variant (see at_set_variant).  1D: 0 automatic, 1/2/3 = 16/8/4
+        points per thread in fused launches, 4 = the whole grid in one
+        workgroup (one launch per run; small grids only)."""
         _check(lib().at_set_variant(self._ctx, int(v)), "at_set_variant")
 
     def set_graph(self, on: bool = True):
@@ -346,7 +349,8 @@ class Stepper:
 
     @property
     def variant(self) -> int:
-        """Kernel variant in use (1D: 0 automatic, 1/2/3 = 16/8/4 points per thread)."""
+        """Kernel variant in use (1D: 0 automatic, 1/2/3 = 16/8/4 points per thread,
+        4 = the whole grid in one workgroup)."""
         v = ctypes.c_int32()
         _check(lib().at_query(self._ctx, None, None, None, ctypes.byref(v)), "at_query")
         return int(v.value)

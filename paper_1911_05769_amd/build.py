@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libat.so")
 SOURCES = ["at_api.hip", "at_step1d.hip", "at_adj1d.hip", "at_step3d.hip", "at_ws1d.hip",
-           "at_util.hip"]
+           "at_util.hip", "at_whole1d.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
           "-Wall", "-Wno-unused-function", "-I" + os.path.join(ROOT, "include")]

@@ -43,6 +43,7 @@ at_status fail(at_status st, const char *fmt, ...)
     } while (0)
 
 constexpr uint64_t kAlign = 256;
+constexpr int kWholeVariant = 4;   // 1D: the whole grid in one workgroup
 uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
@@ -297,10 +298,51 @@ Region1D region_1d(const Derived &d, int s, bool allow_plain)
     return r;
 }
 
+// Points per thread of the whole-grid single-workgroup kernel (1D variant 4)
+// for this context, 0 when the grid does not fit one workgroup
+int whole_ppt(const at_ctx *c)
+{
+    const Derived &d = c->d;
+    if (d.dim != 1) return 0;
+    return step1d_whole_ppt(d.N, d.W, d.P, d.order, c->cfg.L + d.m - 1);
+}
+
 at_status launch_1d(at_ctx *c, const double *uin, double *uout, int64_t n0, int s, int publish,
                     double *levels = nullptr)
 {
     const Derived &d = c->d;
+    if (c->variant == kWholeVariant && !levels) {
+        // the whole grid in one workgroup: any number of steps, no rims
+        Step1D a{};
+        a.uin = uin;
+        a.uout = uout;
+        a.ring = c->ring;
+        a.delays = c->delays;
+        a.N = d.N;
+        a.P = d.P;
+        a.W = d.W;
+        a.n0 = n0;
+        a.CH = d.N;
+        a.s = s;
+        a.R = c->lay.R;
+        a.NT = (int)d.P;
+        a.stale = c->cfg.halo_mode;
+        a.publish = publish;
+        a.RL = 0;
+        a.slot0 = (int32_t)(n0 % a.R);
+        a.D = c->cfg.L + d.m - 1;
+        a.levels = nullptr;
+        a.nu = c->cfg.nu;
+        a.dt = c->cfg.dt;
+        a.c1 = d.c1[0];
+        a.c2 = d.c2[0];
+        a.cadv = c->cfg.adv_speed;
+        a.A1 = a.dt * a.c1;
+        a.A2 = a.dt * (a.nu * a.c2);
+        AT_HIP(launch_step1d_whole(a, d.order, c->cfg.adv_mode == 1, c->cfg.arith == 1,
+                                   whole_ppt(c), c->st));
+        return AT_OK;
+    }
     const Region1D rg = region_1d(d, s);
     const int reg = kThreads * rg.ppt;
     Step1D a;
@@ -634,10 +676,18 @@ at_status at_set_adjoint_fuse(at_ctx *c, int32_t s)
 at_status at_set_variant(at_ctx *c, int32_t v)
 {
     if (!c) return fail(AT_ERR_ARG, "null context");
-    const int nv = c->d.dim == 1 ? 4 : at3_variants();
+    const int nv = c->d.dim == 1 ? 5 : at3_variants();
     if (v < 0 || v >= nv) return fail(AT_ERR_ARG, "variant must be in 0..%d", nv - 1);
     if (c->d.dim == 3 && !at3_variant_ok(&c->cfg, v))
         return fail(AT_ERR_ARG, "variant %d needs block widths that are multiples of its tile", v);
+    if (c->d.dim == 1 && v == kWholeVariant) {
+        if (whole_ppt(c) == 0)
+            return fail(AT_ERR_ARG, "variant 4 needs the grid in one workgroup (N <= 256 x 16, "
+                                    "N and the tile width multiples of 4)");
+        c->variant = v;
+        c->fuse = (int)std::min<int64_t>(std::max<int64_t>(c->cfg.nsteps_max, 1), INT32_MAX);
+        return AT_OK;
+    }
     if (c->d.dim == 1) {
         // 0: automatic; 1, 2, 3: 16, 8, 4 points per thread in fused launches
         const int p = v == 0 ? 0 : (v == 1 ? 16 : (v == 2 ? 8 : 4));
@@ -890,6 +940,7 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
                 if (s <= mf && (s > 1 || v == 1)) cands.push_back({v, s});   // one step: one kernel
         }
         c->d = keep;
+        if (whole_ppt(c) != 0) cands.push_back({kWholeVariant, 0});   // one launch per run
         if (cands.empty()) cands.push_back({c->variant, 1});
     } else {
         for (int v = 0; v < at3_variants(); ++v)
@@ -908,6 +959,12 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
     at_status st = AT_OK;
     // select a candidate: the variant (1D: points per thread) and steps per launch
     auto choose = [&](std::pair<int, int> vs) {
+        if (c->d.dim == 1 && vs.first == kWholeVariant) {
+            c->d.fppt = fused_ppt(c->d);          // the regular layout, for the adjoint's rebuild
+            c->variant = kWholeVariant;
+            c->fuse = (int)std::min<int64_t>(c->cfg.nsteps_max, INT32_MAX);
+            return;
+        }
         if (c->d.dim == 1) {
             const int p = vs.first == 1 ? 16 : (vs.first == 2 ? 8 : 4);
             c->d.fppt = p;
@@ -942,7 +999,7 @@ at_status at_autotune(at_ctx *c, const double *u0, double *t1, double *t2, int32
     choose(best);
     AT_HIP(clear_ring(c));
     AT_HIP(hipStreamSynchronize(c->st));
-    if (chosen) *chosen = c->d.dim == 1 ? best.second : best.first;
+    if (chosen) *chosen = c->d.dim == 1 ? c->fuse : best.first;
     return AT_OK;
 }
 

@@ -123,6 +123,10 @@ int step1d_points_per_thread();
 int step1d_plain_points_per_thread();
 hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, bool fma, int ppt,
                          int64_t nblocks, hipStream_t st);
+size_t step1d_whole_lds_bytes(int order, int64_t P, int D);
+int step1d_whole_ppt(int64_t N, int64_t W, int64_t P, int order, int D);
+hipError_t launch_step1d_whole(const Step1D &a, int order, bool linear, bool fma, int ppt,
+                               hipStream_t st);
 hipError_t launch_step1d_batch(const Step1D *descs, const int2 *tbl, int64_t nblocks, int order,
                                bool linear, bool fma, int ppt, int64_t n0, int flip, size_t lds,
                                hipStream_t st);
