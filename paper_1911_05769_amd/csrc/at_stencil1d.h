@@ -68,6 +68,26 @@ __device__ __forceinline__ double update(const double *nb, double u, const Step1
     return u + a.dt * F;
 }
 
+// Exact order only: the increment dt*F of update(), so that u' = u + dt*F can
+// be formed by the caller after every other read of u (the same operations)
+template <int ORDER, bool LINEAR>
+__device__ __forceinline__ double increment(const double *nb, double u, const Step1D &a)
+{
+    double D1, D2;
+    if constexpr (ORDER == 2) {
+        const double l1 = nb[0], r1 = nb[1];
+        D1 = (r1 - l1) * a.c1;
+        D2 = (fma(-2.0, u, r1) + l1) * a.c2;
+    } else {
+        const double l2 = nb[0], l1 = nb[1], r1 = nb[2], r2 = nb[3];
+        D1 = fma(8.0, r1 - l1, -(r2 - l2)) * a.c1;
+        D2 = (fma(16.0, r1 + l1, -(30.0 * u)) - (r2 + l2)) * a.c2;
+    }
+    const double adv = LINEAR ? a.cadv : u;
+    const double F = a.nu * D2 - adv * D1;
+    return a.dt * F;
+}
+
 }  // namespace
 
 }  // namespace atk

@@ -464,17 +464,32 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
                 }
             }
         }
-        // ---- the standard stencil on every point
-        double res[PPT];
+        // ---- the standard stencil on every point.  Exact order: every increment
+        // dt*F first, then u' = u + dt*F, so that the add is the last read of
+        // each old value and the new level takes its register (no copies)
+        if constexpr (!FMA) {
+            double g[PPT];
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) {
-            double nb[2 * H];
+            for (int j = 0; j < PPT; ++j) {
+                double nb[2 * H];
 #pragma unroll
-            for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
-            res[j] = update<ORDER, LINEAR, FMA>(nb, w[H + j], a);
+                for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
+                g[j] = increment<ORDER, LINEAR>(nb, w[H + j], a);
+            }
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) w[H + j] = w[H + j] + g[j];
+        } else {
+            double res[PPT];
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) {
+                double nb[2 * H];
+#pragma unroll
+                for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
+                res[j] = update<ORDER, LINEAR, FMA>(nb, w[H + j], a);
+            }
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) w[H + j] = res[j];
         }
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) w[H + j] = res[j];
         // every intermediate level of the owned points, straight from registers
         // (used to rebuild a checkpoint segment for the adjoint)
         if (FUSED && a.levels && owns && t + 1 < S) {
