@@ -88,6 +88,68 @@ __device__ __forceinline__ double increment(const double *nb, double u, const St
     return a.dt * F;
 }
 
+// Contracted only: update<ORDER, LINEAR, true> split into the part that reads
+// the neighbours (T1 = D1/c1, T2 = D2/c2) and the part that reads the point
+// itself, u' = fma(A2, T2, fma(-(a*A1), T1, u)): the same operations
+template <int ORDER>
+__device__ __forceinline__ void contracted_terms(const double *nb, double u, double &T1,
+                                                 double &T2)
+{
+    if constexpr (ORDER == 2) {
+        T1 = nb[1] - nb[0];
+        T2 = fma(-2.0, u, nb[1]) + nb[0];
+    } else {
+        T1 = fma(8.0, nb[2] - nb[1], -(nb[3] - nb[0]));
+        T2 = fma(16.0, nb[2] + nb[1], fma(-30.0, u, -(nb[3] + nb[0])));
+    }
+}
+
+template <bool LINEAR>
+__device__ __forceinline__ double contracted_finish(double T1, double T2, double u,
+                                                    const Step1D &a)
+{
+    const double adv = LINEAR ? a.cadv : u;
+    return fma(a.A2, T2, fma(-(adv * a.A1), T1, u));
+}
+
+// One step of a thread's window w[0 .. PPT+2H): points w[H .. H+PPT) with
+// their neighbours' H values on each side.  The new value of point p is
+// formed right after the stencil of point p+H, the last one that reads its
+// old value, so each new value takes the register of its old one (no window
+// copies) and only H+1 pending increments are live at a time.  Every point
+// gets exactly the operations of update(), so the bits are the same.
+template <int ORDER, bool LINEAR, bool FMA, int PPT>
+__device__ __forceinline__ void step_window(double *w, const Step1D &a)
+{
+    constexpr int H = ORDER / 2;
+    if constexpr (!FMA) {
+        double g[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            double nb[2 * H];
+#pragma unroll
+            for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
+            g[j] = increment<ORDER, LINEAR>(nb, w[H + j], a);
+            if (j >= H) w[j] = w[j] + g[j - H];            // point j-H
+        }
+#pragma unroll
+        for (int j = PPT - H; j < PPT; ++j) w[H + j] = w[H + j] + g[j];
+    } else {
+        double T1[PPT], T2[PPT];
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+            double nb[2 * H];
+#pragma unroll
+            for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
+            contracted_terms<ORDER>(nb, w[H + j], T1[j], T2[j]);
+            if (j >= H) w[j] = contracted_finish<LINEAR>(T1[j - H], T2[j - H], w[j], a);
+        }
+#pragma unroll
+        for (int j = PPT - H; j < PPT; ++j)
+            w[H + j] = contracted_finish<LINEAR>(T1[j], T2[j], w[H + j], a);
+    }
+}
+
 }  // namespace
 
 }  // namespace atk

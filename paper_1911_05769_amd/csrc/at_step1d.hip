@@ -65,16 +65,45 @@ __device__ __forceinline__ bool publish_level(const Step1D &a, int t, int S)
     return a.publish == 1 || (a.publish == 2 && t + a.D >= S);
 }
 
-// Level n0 of a region of E points that starts at periodic index G0w (in
-// [0, N)) into the padded LDS stage (point r at r + r/PPT), 0 past E.  Every
-// thread issues all of its PPT loads before its first LDS write, so their
-// latencies overlap.  Indices are wrapped into [0, N) (one subtraction when
-// the grid is at least one region wide), so every load is in bounds; the
-// values past E are loaded and dropped.
+// The region's field passes through a padded LDS stage (point r of a part at
+// r + r/PPT, so that neither the coalesced accesses nor the per-thread ones
+// conflict on banks) in stage_parts() parts: at 16 points per thread in two
+// halves of 2048 points, which keeps the stage at 17 KB instead of 34 KB so
+// that LDS does not cap the workgroups per CU below what registers allow.
 template <int PPT>
-__device__ __forceinline__ void stage_region(const double *__restrict__ uin, int64_t N,
-                                             int64_t G0w, int E, int tid, double *stage)
+__device__ __forceinline__ constexpr int stage_parts() { return PPT >= 16 ? 2 : 1; }
+
+// doubles of one stage part at ppt points per thread
+__host__ __device__ constexpr int stage_doubles(int ppt)
 {
+    return (kThreads * ppt + kThreads) / (ppt >= 16 ? 2 : 1);
+}
+
+// where the edge history of the aligned kernels starts: after both the stage
+// and the exchange buffers, so that the prologue can fill it while the stage
+// is in use
+template <int PPT>
+__device__ __forceinline__ constexpr int aligned_history_offset(int H)
+{
+    return stage_doubles(PPT) > 2 * kThreads * 2 * H ? stage_doubles(PPT) : 2 * kThreads * 2 * H;
+}
+
+// Level n0 of a region of E points that starts at periodic index G0w (in
+// [0, N)) into wp[0 .. PPT) of every thread (thread tid holds region points
+// tid*PPT ..), 0 past E.  Every thread issues all of its PPT loads before its
+// first LDS write, so their latencies overlap.  Indices are wrapped into
+// [0, N) (one subtraction when the grid is at least one region wide), so
+// every load is in bounds; the values past E are loaded and dropped.
+// early() runs once the loads are issued, before the first stage write.  Ends
+// with a barrier: the stage may be reused at once.
+template <int PPT, typename Early>
+__device__ __forceinline__ void load_window(const double *__restrict__ uin, int64_t N,
+                                            int64_t G0w, int E, int tid, double *stage,
+                                            double *wp, Early early)
+{
+    constexpr int PARTS = stage_parts<PPT>();
+    constexpr int IT = PPT / PARTS;                 // loads per thread in one part
+    constexpr int TP = kThreads / PARTS;            // threads whose points a part holds
     double v[PPT];
     if (N >= (int64_t)kThreads * PPT) {
 #pragma unroll
@@ -87,10 +116,46 @@ __device__ __forceinline__ void stage_region(const double *__restrict__ uin, int
 #pragma unroll
         for (int it = 0; it < PPT; ++it) v[it] = uin[(G0w + it * kThreads + tid) % N];
     }
+    early();    // LDS writes of values loaded before these (outside the stage)
 #pragma unroll
-    for (int it = 0; it < PPT; ++it) {
-        const int r = it * kThreads + tid;
-        stage[r + r / PPT] = r < E ? v[it] : 0.0;
+    for (int h = 0; h < PARTS; ++h) {
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int rr = i * kThreads + tid;      // point h*IT*kThreads + rr of the region
+            stage[rr + rr / PPT] = h * IT * kThreads + rr < E ? v[h * IT + i] : 0.0;
+        }
+        __syncthreads();
+        if (tid / TP == h) {
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) wp[j] = stage[(tid - h * TP) * (PPT + 1) + j];
+        }
+        __syncthreads();
+    }
+}
+
+// The inverse: the points wp[0 .. PPT) of every thread through the stage to
+// out[r - lo] for the region points r in [lo, hi), coalesced
+template <int PPT>
+__device__ __forceinline__ void store_window(const double *wp, int tid, double *stage, int lo,
+                                             int hi, double *__restrict__ out)
+{
+    constexpr int PARTS = stage_parts<PPT>();
+    constexpr int IT = PPT / PARTS;
+    constexpr int TP = kThreads / PARTS;
+#pragma unroll
+    for (int h = 0; h < PARTS; ++h) {
+        __syncthreads();
+        if (tid / TP == h) {
+#pragma unroll
+            for (int j = 0; j < PPT; ++j) stage[(tid - h * TP) * (PPT + 1) + j] = wp[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int rr = i * kThreads + tid;
+            const int r = h * IT * kThreads + rr;
+            if (r >= lo && r < hi) out[r - lo] = stage[rr + rr / PPT];
+        }
     }
 }
 
@@ -101,7 +166,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
     constexpr int M = (ORDER == 2) ? 2 : 3;
     constexpr int PPT = kPPT;
     extern __shared__ double lds[];
-    double *stage = lds;                                  // [kThreads*PPT + kThreads]
+    double *stage = lds;                                  // one part of the stage (load_window)
     double *xch = lds;                                    // [2][kThreads][2H]  (aliases stage)
     double *eh = lds + 2 * kThreads * 2 * H;              // [D+s-1][NT][2][H]  (aliases stage)
 
@@ -115,14 +180,10 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
     if (G0w < 0) G0w += a.N;
 
     // ---- level n0 of the region: coalesced loads -> LDS -> registers
-    stage_region<PPT>(a.uin, a.N, G0w, E, tid, stage);
-    __syncthreads();
     double w[PPT + 2 * H];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) w[H + j] = stage[tid * PPT + j + tid];
+    load_window<PPT>(a.uin, a.N, G0w, E, tid, stage, w + H, [] {});
 #pragma unroll
     for (int q = 0; q < H; ++q) { w[q] = 0.0; w[PPT + H + q] = 0.0; }
-    __syncthreads();
 
     // ---- tile bookkeeping of this thread's first point
     const int rp0 = tid * PPT;                            // region position of point 0
@@ -238,15 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_step1d(Step1D a)
     }
 
     // ---- level n0+s of the owned points: registers -> LDS -> coalesced stores
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) stage[tid * PPT + j + tid] = w[H + j];
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < PPT; ++it) {
-        const int r = it * kThreads + tid;
-        if (r >= sh && r < sh + owned) a.uout[c0 + (r - sh)] = stage[r + r / PPT];
-    }
+    store_window<PPT>(w + H, tid, stage, sh, sh + (int)owned, a.uout + c0);
 }
 
 
@@ -268,9 +321,9 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     constexpr int H = ORDER / 2;
     constexpr int M = (ORDER == 2) ? 2 : 3;
     extern __shared__ double lds[];
-    double *stage = lds;                                  // [kThreads*PPT + kThreads]
+    double *stage = lds;                                  // one part of the stage (load_window)
     double *xch = lds;                                    // [2][kThreads][2H]  (aliases stage)
-    double *eh = lds + 2 * kThreads * 2 * H;              // [D+s-1][NT][2][H]  (aliases stage)
+    double *eh = lds + aligned_history_offset<PPT>(H);    // [D+s-1][NT][2][H]  (after both)
 
     const int tid = threadIdx.x;
     const int64_t c0 = chunk * a.CH;
@@ -285,8 +338,9 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     // ---- sources of the LDS copies of this launch's delays and of the ring
     // levels below n0 (eh row d holds level n0 - D + d; kd[(t*NT + tl)*2 +
     // side] the delay of region tile tl's face at level n0 + t).  A thread's
-    // first element of each is loaded together with the field, so that its
-    // latency overlaps theirs.
+    // first element of each is loaded before the field and written to LDS
+    // (which the stage does not overlap) as soon as the field loads are
+    // issued: their latencies overlap, and no register holds them longer.
     const int D = a.D;
     int8_t *kd = reinterpret_cast<int8_t *>(eh + (size_t)(D + S - 1) * a.NT * 2 * H);
     // AT halo values of the region's tile faces, one step at a time
@@ -324,19 +378,18 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
         }
     }
 
-    stage_region<PPT>(a.uin, a.N, G0w, E, tid, stage);
-    __syncthreads();
     double w[PPT + 2 * H];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) w[H + j] = stage[tid * PPT + j + tid];
+    load_window<PPT>(a.uin, a.N, G0w, E, tid, stage, w + H, [&] {
+        if constexpr (FUSED) {
+            if (tid < nk) kd[tid] = k_first;
+            if (e_first_at >= 0) eh[tid] = e_first;
+        }
+    });
 #pragma unroll
     for (int q = 0; q < H; ++q) { w[q] = 0.0; w[PPT + H + q] = 0.0; }
-    __syncthreads();
 
     if constexpr (FUSED) {
-        if (tid < nk) kd[tid] = k_first;
         for (int e = tid + kThreads; e < nk; e += kThreads) kd[e] = a.delays[kd_src(e)];
-        if (e_first_at >= 0) eh[tid] = e_first;
         for (int e = tid + kThreads; e < nr; e += kThreads) {
             const int64_t at = eh_src(e);
             if (at >= 0) eh[e] = a.ring[at];
@@ -464,32 +517,9 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
                 }
             }
         }
-        // ---- the standard stencil on every point.  Exact order: every increment
-        // dt*F first, then u' = u + dt*F, so that the add is the last read of
-        // each old value and the new level takes its register (no copies)
-        if constexpr (!FMA) {
-            double g[PPT];
-#pragma unroll
-            for (int j = 0; j < PPT; ++j) {
-                double nb[2 * H];
-#pragma unroll
-                for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
-                g[j] = increment<ORDER, LINEAR>(nb, w[H + j], a);
-            }
-#pragma unroll
-            for (int j = 0; j < PPT; ++j) w[H + j] = w[H + j] + g[j];
-        } else {
-            double res[PPT];
-#pragma unroll
-            for (int j = 0; j < PPT; ++j) {
-                double nb[2 * H];
-#pragma unroll
-                for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
-                res[j] = update<ORDER, LINEAR, FMA>(nb, w[H + j], a);
-            }
-#pragma unroll
-            for (int j = 0; j < PPT; ++j) w[H + j] = res[j];
-        }
+        // ---- the standard stencil on every point, each new value formed after
+        // the last stencil that reads its old value (same operations as update())
+        step_window<ORDER, LINEAR, FMA, PPT>(w, a);
         // every intermediate level of the owned points, straight from registers
         // (used to rebuild a checkpoint segment for the adjoint)
         if (FUSED && a.levels && owns && t + 1 < S) {
@@ -499,19 +529,15 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
         }
     }
 
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) stage[tid * PPT + j + tid] = w[H + j];
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < PPT; ++it) {
-        const int r = it * kThreads + tid;
-        if (r >= a.RL && r < a.RL + owned) a.uout[c0 + (r - a.RL)] = stage[r + r / PPT];
-    }
+    store_window<PPT>(w + H, tid, stage, a.RL, a.RL + owned, a.uout + c0);
 }
 
+// Five waves per SIMD (at most 96 VGPRs): with the stage in two parts the
+// LDS of a 16-point region allows five workgroups per CU, and the step loop
+// fits the registers without spilling
 template <int ORDER, bool LINEAR, bool FMA, int PPT>
-__global__ __launch_bounds__(kThreads) void k_step1d_aligned(Step1D a)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5)))
+void k_step1d_aligned(Step1D a)
 {
     step1d_aligned_body<ORDER, LINEAR, FMA, true, PPT>(a, blockIdx.x);
 }
@@ -528,9 +554,8 @@ __global__ __launch_bounds__(kThreads) void k_step1d_plain(Step1D a)
 // instance descriptors carry each instance's grid, ring, delays and
 // coefficients; flip = 1 swaps the field pointers (ping-pong launches).
 template <int ORDER, bool LINEAR, bool FMA, int PPT>
-__global__ __launch_bounds__(kThreads) void k_step1d_aligned_batch(const Step1D *descs,
-                                                                   const int2 *tbl, int64_t n0,
-                                                                   int flip)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5)))
+void k_step1d_aligned_batch(const Step1D *descs, const int2 *tbl, int64_t n0, int flip)
 {
     const int2 e = tbl[blockIdx.x];
     Step1D a = descs[e.x];
@@ -552,12 +577,15 @@ int step1d_plain_points_per_thread() { return kPPTPlain; }
 size_t step1d_lds_bytes(int order, int s, int NT, int D, int ppt, bool dense)
 {
     const int H = order / 2;
-    const size_t stage = (size_t)kThreads * ppt + kThreads;
-    // exchange buffers, edge history of D + s - 1 levels, delays (bytes), and
-    // for the batched kernel's dense form the AT halo table [2][NT][2][H]
-    const size_t steps = (size_t)2 * kThreads * 2 * H + (size_t)(D + s - 1) * NT * 2 * H +
-                         ((size_t)s * NT * 2 + 7) / 8 + (dense ? (size_t)2 * NT * 2 * H : 0);
-    return 8 * (stage > steps ? stage : steps);
+    const size_t stage = (size_t)stage_doubles(ppt);
+    const size_t xch = (size_t)2 * kThreads * 2 * H;
+    // the stage part or the exchange buffers, then the edge history of D + s - 1
+    // levels, the delays (bytes) and, for the batched kernel's dense form, the
+    // AT halo table [2][NT][2][H] (the general kernel's layout, whose history
+    // follows the exchange buffers, fits in the same size)
+    const size_t hist = (size_t)(D + s - 1) * NT * 2 * H + ((size_t)s * NT * 2 + 7) / 8 +
+                        (dense ? (size_t)2 * NT * 2 * H : 0);
+    return 8 * ((stage > xch ? stage : xch) + hist);
 }
 
 hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, bool fma, int ppt,
@@ -566,7 +594,7 @@ hipError_t launch_step1d(const Step1D &a, int order, bool linear, bool aligned, 
     const bool plain = aligned && a.s == 1 && ppt == kPPTPlain;
     size_t lds = step1d_lds_bytes(order, a.s, a.NT, a.D, aligned ? ppt : kPPT, false);
     if (plain) {
-        const size_t stage = (size_t)kThreads * kPPTPlain + kThreads;
+        const size_t stage = (size_t)stage_doubles(kPPTPlain);
         const size_t xch = (size_t)2 * kThreads * order;
         lds = 8 * (stage > xch ? stage : xch);
     }

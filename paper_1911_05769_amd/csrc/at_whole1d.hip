@@ -137,31 +137,9 @@ __global__ __launch_bounds__(kWT) void k_step1d_whole(Step1D a)
                     }
                 }
             }
-            // ---- the standard stencil on every point (exact order: the increments
-            // first, then u' = u + dt*F, each add the last read of its old value)
-            if constexpr (!FMA) {
-                double g[PPT];
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    double nb[2 * H];
-#pragma unroll
-                    for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
-                    g[j] = increment<ORDER, LINEAR>(nb, w[H + j], a);
-                }
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) w[H + j] = w[H + j] + g[j];
-            } else {
-                double res[PPT];
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) {
-                    double nb[2 * H];
-#pragma unroll
-                    for (int q = 0; q < H; ++q) { nb[q] = w[j + q]; nb[H + q] = w[j + H + 1 + q]; }
-                    res[j] = update<ORDER, LINEAR, FMA>(nb, w[H + j], a);
-                }
-#pragma unroll
-                for (int j = 0; j < PPT; ++j) w[H + j] = res[j];
-            }
+            // ---- the standard stencil on every point, each new value formed after
+            // the last stencil that reads its old value (same operations as update())
+            step_window<ORDER, LINEAR, FMA, PPT>(w, a);
         }
         kl = kl2;
         kr = kr2;
