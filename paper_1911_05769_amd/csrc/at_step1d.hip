@@ -490,27 +490,33 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
                     }
                 }
             } else {
+                // both tile sides in one pass: a lane that starts a tile takes its
+                // left halo, one that ends a tile its right halo, with the same
+                // arithmetic; a lane that does both (a tile PPT points wide) takes
+                // its right halo in a second pass
+                const bool both = lo_edge && hi_edge;
 #pragma unroll
-                for (int side = 0; side < 2; ++side) {
-                    const int kk = side == 0 ? kl : kr;
+                for (int pass = 0; pass < 2; ++pass) {
+                    const bool left = pass == 0 && lo_edge;
+                    const int kk = pass == 0 ? (lo_edge ? kl : kr) : (both ? kr : 0);
                     if (kk > 0) {
-                        const int stl = side == 0 ? tl0 - 1 : tl0 + 1;
-                        const int64_t stp = side == 0 ? tpl : tpr;
-                        const int sside = 1 - side;
+                        const int stl = left ? tl0 - 1 : tl0 + 1;
+                        const int64_t stp = left ? tpl : tpr;
+                        const int sside = left ? 1 : 0;
 #pragma unroll
                         for (int q = 0; q < H; ++q) {
                             double vv[3] = {0.0, 0.0, 0.0};
 #pragma unroll
                             for (int jj = 0; jj < M; ++jj) {
                                 if (jj == 0 || !a.stale) {
-                                    const int64_t lev = n - kk - jj;
+                                    const int dl = t - kk - jj;        // level n - k - jj, from n0
                                     vv[jj] = FUSED
-                                        ? eh[((((int)(lev - a.n0) + D) * a.NT + stl) * 2 + sside) * H + q]
-                                        : a.ring[((ring_slot(a, lev - a.n0) * a.P + stp) * 2 + sside) * H + q];
+                                        ? eh[(((dl + D) * a.NT + stl) * 2 + sside) * H + q]
+                                        : a.ring[((ring_slot(a, dl) * a.P + stp) * 2 + sside) * H + q];
                                 }
                             }
                             const double hv = extrap<FMA>(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
-                            if (side == 0) w[q] = hv;
+                            if (left) w[q] = hv;
                             else w[PPT + H + q] = hv;
                         }
                     }
