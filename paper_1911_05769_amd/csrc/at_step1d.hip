@@ -342,10 +342,18 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     // (which the stage does not overlap) as soon as the field loads are
     // issued: their latencies overlap, and no register holds them longer.
     const int D = a.D;
-    int8_t *kd = reinterpret_cast<int8_t *>(eh + (size_t)(D + S - 1) * a.NT * 2 * H);
+    // DENSE (the batched kernel, whose regions hold many tiles) keeps the edge
+    // history as a ring of D + 2 levels instead of all D + s - 1, so that its
+    // LDS does not grow with s: level n0 + x - D in row x mod HR
+    const int HR = DENSE ? D + 2 : D + S - 1;
+    auto hrow = [&](int x) -> int {                 // x in [0, 2 HR)
+        if constexpr (DENSE) return x >= HR ? x - HR : x;
+        else return x;
+    };
+    int8_t *kd = reinterpret_cast<int8_t *>(eh + (size_t)HR * a.NT * 2 * H);
     // AT halo values of the region's tile faces, one step at a time
     // (double-buffered): [2][NT][2][H], after the delay bytes
-    double *hal = eh + (size_t)(D + S - 1) * a.NT * 2 * H + ((size_t)S * a.NT * 2 + 7) / 8;
+    double *hal = eh + (size_t)HR * a.NT * 2 * H + ((size_t)S * a.NT * 2 + 7) / 8;
     int64_t tb = floordiv(G0, a.W) % a.P;
     if (tb < 0) tb += a.P;
     const int nk = FUSED ? S * a.NT * 2 : 0;
@@ -414,7 +422,7 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     const bool owns = rp0 >= a.RL && rp0 < a.RL + owned;
     const int64_t F = 2 * a.P;
 
-    for (int t = 0; t < S; ++t) {
+    for (int t = 0, tr = 0; t < S; ++t, tr = (DENSE && tr + 1 == HR) ? 0 : tr + 1) {
         const int64_t n = a.n0 + t;
         const int64_t slot = ring_slot(a, t);
         // ---- record this level's tile edges (LDS history; ring when owned)
@@ -423,11 +431,11 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
 #pragma unroll
             for (int q = 0; q < H; ++q) {
                 if (lo_edge) {
-                    if (FUSED && t < S - 1) eh[(((t + D) * a.NT + tl0) * 2 + 0) * H + q] = w[H + q];
+                    if (FUSED && t < S - 1) eh[((hrow(tr + D) * a.NT + tl0) * 2 + 0) * H + q] = w[H + q];
                     if (pub && owns) a.ring[((slot * a.P + tp0) * 2 + 0) * H + q] = w[H + q];
                 }
                 if (hi_edge) {
-                    if (FUSED && t < S - 1) eh[(((t + D) * a.NT + tl0) * 2 + 1) * H + q] = w[PPT + q];
+                    if (FUSED && t < S - 1) eh[((hrow(tr + D) * a.NT + tl0) * 2 + 1) * H + q] = w[PPT + q];
                     if (pub && owns) a.ring[((slot * a.P + tp0) * 2 + 1) * H + q] = w[PPT + q];
                 }
             }
@@ -455,7 +463,7 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
 #pragma unroll
                     for (int jj = 0; jj < M; ++jj)
                         if (jj == 0 || !a.stale)
-                            vv[jj] = eh[(((t - kk - jj + D) * a.NT + stl) * 2 + (1 - side)) * H + q];
+                            vv[jj] = eh[((hrow(tr + D - kk - jj) * a.NT + stl) * 2 + (1 - side)) * H + q];
                     halt[e] = extrap<FMA>(kk, a.stale != 0, vv[0], vv[1], vv[2], M);
                 }
             }
@@ -511,7 +519,7 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
                                 if (jj == 0 || !a.stale) {
                                     const int dl = t - kk - jj;        // level n - k - jj, from n0
                                     vv[jj] = FUSED
-                                        ? eh[(((dl + D) * a.NT + stl) * 2 + sside) * H + q]
+                                        ? eh[((hrow(tr + D - kk - jj) * a.NT + stl) * 2 + sside) * H + q]
                                         : a.ring[((ring_slot(a, dl) * a.P + stp) * 2 + sside) * H + q];
                                 }
                             }
@@ -586,10 +594,11 @@ size_t step1d_lds_bytes(int order, int s, int NT, int D, int ppt, bool dense)
     const size_t stage = (size_t)stage_doubles(ppt);
     const size_t xch = (size_t)2 * kThreads * 2 * H;
     // the stage part or the exchange buffers, then the edge history of D + s - 1
-    // levels, the delays (bytes) and, for the batched kernel's dense form, the
-    // AT halo table [2][NT][2][H] (the general kernel's layout, whose history
+    // levels (the batched kernel's dense form: a ring of D + 2), the delays
+    // (bytes) and, for the dense form, the AT halo table [2][NT][2][H] (the general kernel's layout, whose history
     // follows the exchange buffers, fits in the same size)
-    const size_t hist = (size_t)(D + s - 1) * NT * 2 * H + ((size_t)s * NT * 2 + 7) / 8 +
+    const size_t rows = dense ? (size_t)D + 2 : (size_t)(D + s - 1);      // the edge history
+    const size_t hist = rows * NT * 2 * H + ((size_t)s * NT * 2 + 7) / 8 +
                         (dense ? (size_t)2 * NT * 2 * H : 0);
     return 8 * ((stage > xch ? stage : xch) + hist);
 }
