@@ -380,19 +380,40 @@ __global__ __launch_bounds__(kThreads) void k_adj1d_fused(AdjF a)
             lhi[q] = tid < kThreads - 1 ? buf[(0 * NS + q) * kThreads + tid + 1] : 0.0;
             uhi[q] = tid < kThreads - 1 ? buf[(1 * NS + q) * kThreads + tid + 1] : 0.0;
         }
+        // ---- the LDS values of this step's edge work, all loaded before the
+        // first is used so that their latencies overlap: the delays of this
+        // tile's faces, and the delays and gathered sums at level n of the
+        // neighbours' faces that this thread's edge points feed
+        const int krow = (int)(n - nlo);
+        const bool lo_src = lo_edge && tid > 0;   // region ends: no source tile in the tables
+        const bool hi_src = hi_edge && tid < kThreads - 1;
+        int kown[2] = {0, 0}, knb[2] = {1, 1};
+        double gth[2][H];
+#pragma unroll
+        for (int q = 0; q < H; ++q) { gth[0][q] = 0.0; gth[1][q] = 0.0; }
+        if (lo_edge) kown[0] = kd[(krow * NT + tl0) * 2 + 0];
+        if (hi_edge) kown[1] = kd[(krow * NT + tl0) * 2 + 1];
+        if (hi_src) {                             // feeds the next tile's low face
+            knb[0] = kd[(krow * NT + tl0 + 1) * 2 + 0];
+#pragma unroll
+            for (int q = 0; q < H; ++q) gth[0][q] = gt[((krow * NT + tl0 + 1) * 2 + 0) * H + q];
+        }
+        if (lo_src) {                             // feeds the previous tile's high face
+            knb[1] = kd[(krow * NT + tl0 - 1) * 2 + 1];
+#pragma unroll
+            for (int q = 0; q < H; ++q) gth[1][q] = gt[((krow * NT + tl0 - 1) * 2 + 1) * H + q];
+        }
         // ---- u window with the forward AT halo across the tile faces
         double uw[PPT + 2 * H];
 #pragma unroll
         for (int q = 0; q < H; ++q) { uw[q] = ulo[q]; uw[PPT + H + q] = uhi[q]; }
 #pragma unroll
         for (int j = 0; j < PPT; ++j) uw[H + j] = uc[j];
-        const int krow = (int)(n - nlo);
         if (lo_edge || hi_edge) {
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
-                // region ends: no source tile inside the tables (outside the owned cone)
-                if (side == 0 ? !(lo_edge && tid > 0) : !(hi_edge && tid < kThreads - 1)) continue;
-                const int kk = kd[(krow * NT + tl0) * 2 + side];
+                if (side == 0 ? !lo_src : !hi_src) continue;
+                const int kk = kown[side];
                 if (kk > 0) {
                     const int stl = side == 0 ? tl0 - 1 : tl0 + 1;
 #pragma unroll
@@ -458,16 +479,13 @@ __global__ __launch_bounds__(kThreads) void k_adj1d_fused(AdjF a)
             // delayed halo contributions gathered over steps n .. n+L+m-1
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
-                const bool feeds = side == 0 ? (hi_edge && tid < kThreads - 1 && j >= PPT - H)
-                                             : (lo_edge && tid > 0 && j < H);
+                const bool feeds = side == 0 ? (hi_src && j >= PPT - H) : (lo_src && j < H);
                 if (!feeds) continue;
-                const int stl = side == 0 ? tl0 + 1 : tl0 - 1;
-                const int fs = side == 0 ? 0 : 1;
                 const int q = side == 0 ? j - (PPT - H) : j;
                 // later levels' contributions, accumulated newest first by their
                 // producers; then this level's own (k = 0: the raw neighbour)
-                double g = gt[((krow * NT + stl) * 2 + fs) * H + q];
-                if (kd[(krow * NT + stl) * 2 + fs] == 0)
+                double g = gth[side][q];
+                if (knb[side] == 0)
                     g += hweight(0, stale, 0, M) * (side == 0 ? mu_lo(q) : mu_hi(q));
                 acc += g;
             }
@@ -478,7 +496,7 @@ __global__ __launch_bounds__(kThreads) void k_adj1d_fused(AdjF a)
         // earlier levels of this launch that it feeds (n-k-j, weight dH/dv_j),
         // and to the ring for later launches
         auto scatter = [&](int side, int q, double m) {
-            const int kk = kd[(krow * NT + tl0) * 2 + side];
+            const int kk = kown[side];
             const int need = (kk == 0 || stale) ? 1 : M;
             for (int jw = 0; jw < need; ++jw) {
                 const int64_t nt2 = n - kk - jw;      // level this contribution belongs to
