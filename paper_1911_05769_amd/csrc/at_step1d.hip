@@ -67,16 +67,15 @@ __device__ __forceinline__ bool publish_level(const Step1D &a, int t, int S)
 
 // The region's field passes through a padded LDS stage (point r of a part at
 // r + r/PPT, so that neither the coalesced accesses nor the per-thread ones
-// conflict on banks) in stage_parts() parts: at 16 points per thread in two
+// conflict on banks) in stage_parts(PPT) parts: at 16 points per thread in two
 // halves of 2048 points, which keeps the stage at 17 KB instead of 34 KB so
 // that LDS does not cap the workgroups per CU below what registers allow.
-template <int PPT>
-__device__ __forceinline__ constexpr int stage_parts() { return PPT >= 16 ? 2 : 1; }
+__host__ __device__ constexpr int stage_parts(int ppt) { return ppt >= 16 ? 2 : 1; }
 
 // doubles of one stage part at ppt points per thread
 __host__ __device__ constexpr int stage_doubles(int ppt)
 {
-    return (kThreads * ppt + kThreads) / (ppt >= 16 ? 2 : 1);
+    return (kThreads * ppt + kThreads) / stage_parts(ppt);
 }
 
 // where the edge history of the aligned kernels starts: after both the stage
@@ -101,7 +100,7 @@ __device__ __forceinline__ void load_window(const double *__restrict__ uin, int6
                                             int64_t G0w, int E, int tid, double *stage,
                                             double *wp, Early early)
 {
-    constexpr int PARTS = stage_parts<PPT>();
+    constexpr int PARTS = stage_parts(PPT);
     constexpr int IT = PPT / PARTS;                 // loads per thread in one part
     constexpr int TP = kThreads / PARTS;            // threads whose points a part holds
     double v[PPT];
@@ -139,7 +138,7 @@ template <int PPT>
 __device__ __forceinline__ void store_window(const double *wp, int tid, double *stage, int lo,
                                              int hi, double *__restrict__ out)
 {
-    constexpr int PARTS = stage_parts<PPT>();
+    constexpr int PARTS = stage_parts(PPT);
     constexpr int IT = PPT / PARTS;
     constexpr int TP = kThreads / PARTS;
 #pragma unroll
@@ -323,7 +322,7 @@ __device__ __forceinline__ void step1d_aligned_body(const Step1D &a, int64_t chu
     extern __shared__ double lds[];
     double *stage = lds;                                  // one part of the stage (load_window)
     double *xch = lds;                                    // [2][kThreads][2H]  (aliases stage)
-    double *eh = lds + aligned_history_offset<PPT>(H);    // [D+s-1][NT][2][H]  (after both)
+    double *eh = lds + aligned_history_offset<PPT>(H);    // [HR][NT][2][H]  (after both)
 
     const int tid = threadIdx.x;
     const int64_t c0 = chunk * a.CH;
