@@ -57,7 +57,7 @@ def test_batch_equals_standalone_and_oracle(gpu):
                      st0.delays(), nst)
     assert np.array_equal(refs[2].cpu().numpy(), o)
     b = gpu.Batch.from_workloads(wls)
-    for s in (1, 2, 5, 8, 16, 32):
+    for s in (1, 2, 5, 8, 16, 32, 48, 64):
         if s > b.query()[2]:
             continue
         log("batch fuse", s)
@@ -111,14 +111,21 @@ def test_batch_full_workload_sampled(gpu):
     b = gpu.Batch.from_workloads(wls)
     us = [dev(w.u0) for w in wls]
     ss = [torch.empty_like(u) for u in us]
-    s = b.autotune(us, 40)
-    log("autotuned fuse", s)
-    b.run(us, ss, nst, use_graph=True)
     order = np.argsort([w.n[0] for w in wls])
     sample = list(order[:3]) + list(order[-2:]) + [17, 101, 200]
-    for j in sample:
-        ref, st = standalone(gpu, wls[j], nst)
-        assert torch.equal(us[j], ref), "instance %d" % j
+    refs = {j: standalone(gpu, wls[j], nst)[0] for j in sample}
+    # the autotuned pair (trials as long as the benchmark's), then the largest
+    # steps per launch (the edge-history ring wraps many times per launch)
+    s = b.autotune(us, 128)
+    log("autotuned fuse", s, "variant", b.variant)
+    for fuse in (s, b.query()[2]):
+        b.reset()
+        b.set_fuse(fuse)
+        for u, w in zip(us, wls):
+            u.copy_(dev(w.u0))
+        b.run(us, ss, nst, use_graph=True)
+        for j in sample:
+            assert torch.equal(us[j], refs[j]), "instance %d fuse %d" % (j, fuse)
     for j in order[:2]:
         w = wls[j]
         _, st = standalone(gpu, w, 1)
