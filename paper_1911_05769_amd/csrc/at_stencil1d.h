@@ -32,44 +32,12 @@ __device__ __forceinline__ double extrap(int kk, bool stale, double v0, double v
     return (v0 + dk * d1) + w2 * (d1 - (v1 - v2));
 }
 
-template <int ORDER, bool LINEAR, bool FMA = false>
-__device__ __forceinline__ double update(const double *nb, double u, const Step1D &a)
-{
-    if constexpr (FMA) {
-        // contracted: u' = u + A2*T2 - (a*A1)*T1 with T1 = D1/c1, T2 = D2/c2
-        double T1, T2;
-        if constexpr (ORDER == 2) {
-            T1 = nb[1] - nb[0];
-            T2 = fma(-2.0, u, nb[1]) + nb[0];
-        } else {
-            T1 = fma(8.0, nb[2] - nb[1], -(nb[3] - nb[0]));
-            T2 = fma(16.0, nb[2] + nb[1], fma(-30.0, u, -(nb[3] + nb[0])));
-        }
-        const double adv = LINEAR ? a.cadv : u;
-        return fma(a.A2, T2, fma(-(adv * a.A1), T1, u));
-    }
-    // Exact order: D1 = (8(r1-l1) - (r2-l2))*c1, D2 = ((16(r1+l1) - 30u) - (r2+l2))*c2
-    // (order 2: D1 = (r1-l1)*c1, D2 = ((r1 - 2u) + l1)*c2), each operation rounded
-    // on its own.  A product by 2, 8 or 16 is exact, so fusing it with the
-    // following add into one fma rounds once where the separate pair also
-    // rounds once: the same bits in one instruction instead of two.
-    double D1, D2;
-    if constexpr (ORDER == 2) {
-        const double l1 = nb[0], r1 = nb[1];
-        D1 = (r1 - l1) * a.c1;
-        D2 = (fma(-2.0, u, r1) + l1) * a.c2;
-    } else {
-        const double l2 = nb[0], l1 = nb[1], r1 = nb[2], r2 = nb[3];
-        D1 = fma(8.0, r1 - l1, -(r2 - l2)) * a.c1;
-        D2 = (fma(16.0, r1 + l1, -(30.0 * u)) - (r2 + l2)) * a.c2;
-    }
-    const double adv = LINEAR ? a.cadv : u;
-    const double F = a.nu * D2 - adv * D1;
-    return u + a.dt * F;
-}
-
-// Exact order only: the increment dt*F of update(), so that u' = u + dt*F can
-// be formed by the caller after every other read of u (the same operations)
+// Exact order: the increment dt*F, with D1 = (8(r1-l1) - (r2-l2))*c1 and
+// D2 = ((16(r1+l1) - 30u) - (r2+l2))*c2 (order 2: D1 = (r1-l1)*c1,
+// D2 = ((r1 - 2u) + l1)*c2), each operation rounded on its own.  A product by
+// 2, 8 or 16 is exact, so fusing it with the following add into one fma rounds
+// once where the separate pair also rounds once: the same bits in one
+// instruction instead of two.
 template <int ORDER, bool LINEAR>
 __device__ __forceinline__ double increment(const double *nb, double u, const Step1D &a)
 {
@@ -88,9 +56,9 @@ __device__ __forceinline__ double increment(const double *nb, double u, const St
     return a.dt * F;
 }
 
-// Contracted only: update<ORDER, LINEAR, true> split into the part that reads
-// the neighbours (T1 = D1/c1, T2 = D2/c2) and the part that reads the point
-// itself, u' = fma(A2, T2, fma(-(a*A1), T1, u)): the same operations
+// Contracted: u' = u + A2*T2 - (a*A1)*T1 with T1 = D1/c1, T2 = D2/c2, split
+// into the part that reads the neighbours (T1, T2) and the part that reads the
+// point itself, u' = fma(A2, T2, fma(-(a*A1), T1, u))
 template <int ORDER>
 __device__ __forceinline__ void contracted_terms(const double *nb, double u, double &T1,
                                                  double &T2)
@@ -110,6 +78,18 @@ __device__ __forceinline__ double contracted_finish(double T1, double T2, double
 {
     const double adv = LINEAR ? a.cadv : u;
     return fma(a.A2, T2, fma(-(adv * a.A1), T1, u));
+}
+
+// u' of one point from its neighbours nb (points -H..-1, 1..H) and itself
+template <int ORDER, bool LINEAR, bool FMA = false>
+__device__ __forceinline__ double update(const double *nb, double u, const Step1D &a)
+{
+    if constexpr (FMA) {
+        double T1, T2;
+        contracted_terms<ORDER>(nb, u, T1, T2);
+        return contracted_finish<LINEAR>(T1, T2, u, a);
+    }
+    return u + increment<ORDER, LINEAR>(nb, u, a);
 }
 
 // One step of a thread's window w[0 .. PPT+2H): points w[H .. H+PPT) with
