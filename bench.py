@@ -316,6 +316,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--fuse", type=int, default=None,
                     help="steps per launch of the headline run (default: autotuned)")
+    ap.add_argument("--batch-fuse", type=int, default=None,
+                    help="batched leg: steps per launch at 16 points per thread (default: autotuned)")
     ap.add_argument("--variant3d", type=int, default=None,
                     help="3D legs: run this kernel variant instead of the autotuned one")
     ap.add_argument("--calibrate", action="store_true",
@@ -463,7 +465,12 @@ def bench_batched(args, torch, at, I):
     batched(False)
     w2, k2 = _timed(torch, lambda: batched(False))
     b.reset()
-    s = b.autotune(u0, 128)
+    if args.batch_fuse:
+        b.set_variant(1)
+        b.set_fuse(args.batch_fuse)
+        s = args.batch_fuse
+    else:
+        s = b.autotune(u0, 128)
     batched(True)                       # capture
     reps = max(1, args.steps)
     tm = Timer(torch)
