@@ -1593,8 +1593,12 @@ at_status at_batch_autotune(at_batch *b, double *const *u0, double *const *t1,
     at_status st = AT_OK;
     for (int v = 1; v <= 3 && st == AT_OK; ++v) {
         st = at_batch_set_variant(b, v);
-        for (int s : cands) {
-            if (st != AT_OK || s > b->max_fuse) break;
+        // largest steps per launch first: a smaller count must be 2% faster to
+        // replace it (fewer launches, and fewer launch tails, on a near tie)
+        for (int ci = (int)(sizeof(cands) / sizeof(cands[0])) - 1; ci >= 0; --ci) {
+            const int s = cands[ci];
+            if (st != AT_OK) break;
+            if (s > b->max_fuse) continue;
             float ms_best = 1e30f;
             for (int rep = 0; rep < 2 && st == AT_OK; ++rep) {
                 st = at_batch_reset(b);
