@@ -341,7 +341,8 @@ at_status at_batch_set_variant(at_batch *b, int32_t variant);
 
 /* Choose the batch's points per thread and steps per launch by timing (same
  * contract as at_autotune, per batch); *chosen receives the steps per
- * launch, at_batch_query both. */
+ * launch, at_batch_query both.  Steps per launch are tried largest first, and
+ * a smaller count replaces a larger one only when it is 2% faster. */
 at_status at_batch_autotune(at_batch *b, double *const *u_dev, double *const *t1,
                             double *const *t2, int32_t trial_steps, int32_t *chosen);
 at_status at_batch_set_fuse(at_batch *b, int32_t fuse_steps);
